@@ -1,0 +1,259 @@
+"""Seeded synthetic inputs for the Godunov step.
+
+This module is the one piece that both the GPU path and the CPU oracle
+consume: it turns prescribed physical fields (density, velocity, pressure)
+into conserved states and lays them out. It contains none of the scheme's own
+arithmetic (no reconstruction, no fluxes, no update, no time step).
+
+The paper's workloads are cosmological AMR runs (Sec. 3, Table 1; Sec. 4) whose
+initial conditions are not available; these generators stand in for them:
+
+* ``sod_patch``       one 32^3 ghost-zoned patch with a planar density and
+                      pressure jump plus 1% density noise (the shock-tube
+                      problem inside a single patch);
+* ``turbulent_box``   a periodic box with log-normal density (sigma_ln = 1)
+                      built from a Gaussian random field with a k^-11/3 power
+                      spectrum and Gaussian random velocities at rms Mach 2,
+                      mimicking the cosmic-web density PDF;
+* ``amr_batch``       thousands of ghost-zoned patches of uneven size
+                      (8^3..32^3) holding a smooth sine background cut by a
+                      planar Mach-3 shock of random orientation, mimicking
+                      patches at refinement fronts;
+* ``smooth_box``      a periodic box of a few low Fourier modes at 5%
+                      amplitude, for gradient checks.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = 5.0 / 3.0
+
+
+def conserved(rho, vx, vy, vz, p, gamma=GAMMA):
+    """Stack (rho, rho v, E) with E = p/(gamma-1) + rho |v|^2 / 2."""
+    rho, vx, vy, vz, p = (np.asarray(a, dtype=np.float64) for a in (rho, vx, vy, vz, p))
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return np.stack([rho, rho * vx, rho * vy, rho * vz, E])
+
+
+def outflow_fill(interior, ng=2):
+    """Ghost-zoned copy of a (5, nz, ny, nx) state with zero-gradient ghosts
+    (every ghost, edges and corners included, copies the nearest interior cell)."""
+    return np.pad(interior, ((0, 0), (ng, ng), (ng, ng), (ng, ng)), mode="edge")
+
+
+def sod_patch(n=32, ng=2, gamma=GAMMA, noise=0.01, seed=0, axis=0):
+    """Shock-tube patch: (rho, p) = (1, 1) for x < 1/2 and (0.125, 0.1) beyond,
+    v = 0, interior density times (1 + noise U(-1, 1)); outflow ghosts.
+    Returns (u_ghosted, dx) with dx = 1/n."""
+    x = (np.arange(n) + 0.5) / n
+    left = x < 0.5
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    left = left.reshape(shape)
+    rho = np.where(left, 1.0, 0.125) * np.ones((n, n, n))
+    p = np.where(left, 1.0, 0.1) * np.ones((n, n, n))
+    if noise:
+        rng = np.random.default_rng(seed)
+        rho = rho * (1.0 + noise * rng.uniform(-1.0, 1.0, size=(n, n, n)))
+    zero = np.zeros((n, n, n))
+    return outflow_fill(conserved(rho, zero, zero, zero, p, gamma), ng), 1.0 / n
+
+
+def gaussian_random_field(n, seed, spectral_index=-11.0 / 3.0):
+    """Zero-mean, unit-variance periodic field whose power spectrum is
+    P(k) ~ k^spectral_index: white noise filtered by k^(spectral_index/2)."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((n, n, n))
+    fk = np.fft.rfftn(white)
+    k1 = np.fft.fftfreq(n) * n
+    kz = np.fft.rfftfreq(n) * n
+    kk = np.sqrt(k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kz[None, None, :] ** 2)
+    amp = np.zeros_like(kk)
+    nz = kk > 0
+    amp[nz] = kk[nz] ** (spectral_index / 2.0)
+    f = np.fft.irfftn(fk * amp, s=(n, n, n), axes=(0, 1, 2))
+    f -= f.mean()
+    return f / f.std()
+
+
+def turbulent_box(n=256, gamma=GAMMA, mach=2.0, sigma_ln=1.0, seeds=(1, 2, 3, 4)):
+    """Periodic (5, n, n, n) state: rho = exp(sigma s - sigma^2/2) with s a
+    k^-11/3 Gaussian random field; velocities independent fields of the same
+    spectrum scaled to rms |v| = mach c_s; p = 0.6 rho / gamma, so c_s^2 = 0.6."""
+    s = gaussian_random_field(n, seeds[0])
+    rho = np.exp(sigma_ln * s - 0.5 * sigma_ln ** 2)
+    vel = [gaussian_random_field(n, sd) for sd in seeds[1:4]]
+    vel = [v - v.mean() for v in vel]
+    rms = math.sqrt(float(np.mean(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)))
+    scale = mach * math.sqrt(0.6) / rms
+    p = 0.6 * rho / gamma
+    return conserved(rho, vel[0] * scale, vel[1] * scale, vel[2] * scale, p, gamma)
+
+
+def _random_unit(rng):
+    v = rng.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def _random_wavevector(rng, kmax):
+    while True:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if np.any(k != 0):
+            return k.astype(np.float64)
+
+
+def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0):
+    """One ghost-zoned patch (5, nz+2ng, ny+2ng, nx+2ng): smooth sine background
+    (rho and p at 1 +- 0.2, |v| <= 0.1) evaluated at cell centres from a random
+    origin, cut by a planar shock of random normal through a random interior
+    point. The post-shock side carries the Rankine-Hugoniot state of a Mach
+    `mach` shock relative to the local background."""
+    origin = rng.uniform(0.0, 1.0, size=3)
+    kr, kp, kv = (_random_wavevector(rng, 2) for _ in range(3))
+    phr, php, phv = rng.uniform(0.0, 2 * math.pi, size=3)
+    ev = _random_unit(rng)
+    normal = _random_unit(rng)
+    through = origin + dx * rng.uniform(0.0, 1.0, size=3) * np.array([nx, ny, nz])
+
+    ix = origin[0] + (np.arange(-ng, nx + ng) + 0.5) * dx
+    iy = origin[1] + (np.arange(-ng, ny + ng) + 0.5) * dx
+    iz = origin[2] + (np.arange(-ng, nz + ng) + 0.5) * dx
+    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+
+    def wave(k, ph):
+        return np.sin(2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+
+    rho1 = 1.0 + 0.2 * wave(kr, phr)
+    p1 = 1.0 + 0.2 * wave(kp, php)
+    vmag = 0.1 * wave(kv, phv)
+    v1 = [vmag * ev[d] for d in range(3)]
+
+    c1 = np.sqrt(gamma * p1 / rho1)
+    m2 = mach * mach
+    ratio = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    pjump = (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)
+    du = (1.0 - 1.0 / ratio) * mach * c1
+    behind = (normal[0] * (X - through[0]) + normal[1] * (Y - through[1])
+              + normal[2] * (Z - through[2])) <= 0.0
+    rho = np.where(behind, rho1 * ratio, rho1)
+    p = np.where(behind, p1 * pjump, p1)
+    v = [np.where(behind, v1[d] + du * normal[d], v1[d]) for d in range(3)]
+    return conserved(rho, v[0], v[1], v[2], p, gamma)
+
+
+@dataclass
+class Batch:
+    """A packed batch of ghost-zoned patches.
+
+    dims[p] = (nx, ny, nz); all arrays of patch p live in flat buffers at the
+    element offsets u_in_off[p] (shape [5][nz+2ng][ny+2ng][nx+2ng]),
+    u_out_off[p] ([5][nz][ny][nx]) and flux_off[p] (six boundary sheets,
+    10 (nz ny + nz nx + ny nx) values)."""
+    dims: np.ndarray
+    ng: int
+    dx: np.ndarray
+    u_in: np.ndarray
+    u_in_off: np.ndarray
+    u_out_off: np.ndarray
+    flux_off: np.ndarray
+    u_out_size: int
+    flux_size: int
+
+    @property
+    def npatch(self):
+        return len(self.dims)
+
+    @property
+    def interior_cells(self):
+        return int(np.prod(self.dims, axis=1).sum())
+
+    def patch_in(self, p):
+        nx, ny, nz = (int(v) for v in self.dims[p])
+        g = self.ng
+        n = 5 * (nz + 2 * g) * (ny + 2 * g) * (nx + 2 * g)
+        return self.u_in[self.u_in_off[p]:self.u_in_off[p] + n].reshape(
+            5, nz + 2 * g, ny + 2 * g, nx + 2 * g)
+
+    def patch_out(self, flat_out, p):
+        nx, ny, nz = (int(v) for v in self.dims[p])
+        return flat_out[self.u_out_off[p]:self.u_out_off[p] + 5 * nx * ny * nz].reshape(5, nz, ny, nx)
+
+    def patch_flux(self, flat_flux, p):
+        nx, ny, nz = (int(v) for v in self.dims[p])
+        return flat_flux[self.flux_off[p]:self.flux_off[p] + 10 * (nz * ny + nz * nx + ny * nx)]
+
+
+def pack_batch(states, ng, dx, order_seed=None):
+    """Pack a list of ghost-zoned (5, gz, gy, gx) states into one Batch.
+    With order_seed, patches are laid out in memory in a seeded random order
+    (the descriptor list keeps the given order)."""
+    npatch = len(states)
+    dims = np.array([[s.shape[3] - 2 * ng, s.shape[2] - 2 * ng, s.shape[1] - 2 * ng]
+                     for s in states], dtype=np.int64)
+    place = np.arange(npatch)
+    if order_seed is not None:
+        place = np.random.default_rng(order_seed).permutation(npatch)
+    in_sizes = np.array([s.size for s in states], dtype=np.int64)
+    out_sizes = 5 * np.prod(dims, axis=1)
+    fl_sizes = 10 * (dims[:, 2] * dims[:, 1] + dims[:, 2] * dims[:, 0] + dims[:, 1] * dims[:, 0])
+
+    def offsets(sizes):
+        off = np.zeros(npatch, dtype=np.int64)
+        run = 0
+        for p in place:
+            off[p] = run
+            run += int(sizes[p])
+        return off, run
+
+    u_in_off, n_in = offsets(in_sizes)
+    u_out_off, n_out = offsets(out_sizes)
+    flux_off, n_fl = offsets(fl_sizes)
+    u_in = np.empty(n_in, dtype=np.float64)
+    for p, s in enumerate(states):
+        u_in[u_in_off[p]:u_in_off[p] + s.size] = s.ravel()
+    dxs = np.full(npatch, float(dx)) if np.isscalar(dx) else np.asarray(dx, dtype=np.float64)
+    return Batch(dims, ng, dxs, u_in, u_in_off, u_out_off, flux_off, n_out, n_fl)
+
+
+def amr_batch(npatch=4096, seed=5, ng=2, dx=1.0 / 256, gamma=GAMMA,
+              sizes=(8, 16, 24, 32), probs=(0.5, 0.3, 0.15, 0.05), mach=3.0):
+    """Batch of cubic patches with edge lengths drawn from `sizes` with
+    probabilities `probs`; each holds a shocked_patch field; packed in a
+    seeded random memory order."""
+    rng = np.random.default_rng(seed)
+    edge = rng.choice(np.asarray(sizes), size=npatch, p=np.asarray(probs))
+    states = [shocked_patch(rng, int(n), int(n), int(n), ng, dx, gamma, mach) for n in edge]
+    return pack_batch(states, ng, dx, order_seed=seed + 1000)
+
+
+def random_patch(nx, ny, nz, ng=2, seed=0, dx=None, gamma=GAMMA, mach=3.0):
+    """Generic test patch: the shocked_patch field of the given extents."""
+    rng = np.random.default_rng(seed)
+    return shocked_patch(rng, nx, ny, nz, ng, 1.0 / 64 if dx is None else dx, gamma, mach)
+
+
+def _mode_sum(n, rng, nmodes=8, kmax=4):
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    f = np.zeros((n, n, n))
+    for _ in range(nmodes):
+        k = _random_wavevector(rng, kmax)
+        ph = rng.uniform(0.0, 2 * math.pi)
+        f += np.sin(2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+    return f / np.max(np.abs(f))
+
+
+def smooth_box(n=128, gamma=GAMMA, amplitude=0.05, seeds=(13, 14, 15, 16, 17, 18)):
+    """Periodic smooth state and a density target: rho, p = 1 + a f_m with f_m
+    a sum of 8 random Fourier modes (integer wavevectors in [-4, 4]^3)
+    normalised to max |f_m| = 1; velocities a c_s f_m. Returns (U0, rho_target)."""
+    rho = 1.0 + amplitude * _mode_sum(n, np.random.default_rng(seeds[0]))
+    p = 1.0 + amplitude * _mode_sum(n, np.random.default_rng(seeds[1]))
+    cs = math.sqrt(gamma)
+    vel = [amplitude * cs * _mode_sum(n, np.random.default_rng(s)) for s in seeds[2:5]]
+    target = 1.0 + amplitude * _mode_sum(n, np.random.default_rng(seeds[5]))
+    return conserved(rho, vel[0], vel[1], vel[2], p, gamma), target
