@@ -1,0 +1,172 @@
+/*
+ * godunov.h -- C ABI of the MI355X (gfx950) Godunov step library, libgodunov.so.
+ *
+ * One call advances the compressible Euler equations of an ideal gas by one
+ * time step on one or many ghost-zoned patches, with a second-order unsplit
+ * MUSCL-Hancock Godunov scheme (the piecewise-linear method family the paper
+ * names in Sec. 2), and hands back the fluxes through each patch boundary
+ * that a multilevel, adaptive-time-step caller needs for coarse-fine flux
+ * correction (Sec. 4). The patch is the paper's GPU work unit: inner cells
+ * plus boundary (ghost) cells already filled by the caller, interpolated
+ * where the patch adjoins another refinement level (Sec. 3).
+ *
+ * Scheme, per step (every array in one call has the same dtype):
+ *   1. conserved U = (rho, rho u, rho v, rho w, E) -> primitive
+ *      W = (rho, u, v, w, p), p = (gamma-1)(E - |rho u|^2/(2 rho)); rho and p
+ *      raised to rho_floor and p_floor (each raise is counted);
+ *   2. undivided limited slopes of W along x, y and z (gd_limiter);
+ *   3. half-step predictor W* = W - dt/(2dx) sum_d A_d(W) dW_d, with A_d the
+ *      primitive-variable Jacobian along d (all three directions, no
+ *      transverse Riemann solves);
+ *   4. face states W_L = W*_i + dW_i/2, W_R = W*_{i+1} - dW_{i+1}/2, floored;
+ *   5. one Riemann flux per face (gd_riemann), Davis wave-speed bounds
+ *      S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R);
+ *   6. U' = U - dt/dx [((F_x+ - F_x-) + (F_y+ - F_y-)) + (F_z+ - F_z-)].
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller; the
+ * library never allocates or frees caller data. Layouts are C order, x
+ * fastest, structure of arrays over the five conserved variables:
+ *   ghosted input  [5][nz+2ng][ny+2ng][nx+2ng]  (ng >= 2; only the interior,
+ *                  face ghosts of depth <= 2 and edge ghosts of depth 1 are
+ *                  read -- corner ghosts are never read)
+ *   periodic input [5][nz][ny][nx]              (neighbours wrap around)
+ *   output         [5][nz][ny][nx]              (interior only)
+ *   boundary flux  six sheets in the order x-, x+, y-, y+, z-, z+, each
+ *                  [5][slow][fast] with (slow, fast) = (z, y) for x sheets,
+ *                  (z, x) for y sheets, (y, x) for z sheets; total
+ *                  10 (nz ny + nz nx + ny nx) values. A sheet holds the face
+ *                  flux F_d exactly as used in step 6 (positive = transport
+ *                  towards +d), per unit area and time; a refluxing caller
+ *                  multiplies by dt and the face area.
+ *
+ * Errors: every entry point returns a gd_status. All argument checks run on
+ * the host before anything is launched; on failure nothing is launched and
+ * gd_last_error() describes the problem. A HIP error from a launch is
+ * returned as GD_E_HIP. Non-physical states are floored and counted, never
+ * reported as errors; NaN inputs propagate to the outputs.
+ *
+ * Ordering: every call is asynchronous and stream-ordered on the HIP stream
+ * passed in (NULL = the null stream); nothing synchronises the host except
+ * gd_get_stats(). One gd_ctx per host thread. Calls that share a gd_ctx
+ * share its device counters, so two of them in flight on different streams
+ * at the same time race; serialise them on one stream.
+ */
+#ifndef GODUNOV_H
+#define GODUNOV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gd_ctx gd_ctx;
+
+typedef enum {
+    GD_OK = 0,
+    GD_E_ARG = -1,          /* invalid argument; nothing was launched */
+    GD_E_HIP = -2,          /* the HIP runtime reported an error */
+    GD_E_NOMEM = -3,        /* the library could not allocate its own scratch */
+    GD_E_UNSUPPORTED = -4   /* valid but not implemented combination */
+} gd_status;
+
+typedef enum { GD_F64 = 0, GD_F32 = 1 } gd_dtype;          /* dtype of every array */
+typedef enum { GD_GHOSTED = 0, GD_PERIODIC = 1 } gd_bc;      /* layout of the input */
+typedef enum { GD_MINMOD = 0, GD_MC = 1, GD_UNLIMITED = 2 } gd_limiter;
+typedef enum { GD_HLLC = 0, GD_HLL = 1 } gd_riemann;
+
+/* Scheme options. minmod(a,b) = 0 unless a, b share a sign, else the one of
+ * smaller magnitude; MC = sign(a) min(2|a|, 2|b|, |a+b|/2) for a, b of one
+ * sign, else 0; unlimited = (a+b)/2. HLLC resolves the contact wave (Toro,
+ * Spruce & Speares 1994); HLL does not (Harten, Lax & van Leer 1983). */
+typedef struct {
+    int32_t dtype;          /* gd_dtype */
+    int32_t bc;             /* gd_bc (batched calls: GD_GHOSTED only) */
+    int32_t limiter;        /* gd_limiter */
+    int32_t riemann;        /* gd_riemann */
+    double rho_floor;       /* >= 0 */
+    double p_floor;         /* >= 0 */
+} gd_opts;
+
+/* One patch of a batched call. Offsets are in ELEMENTS (of the call's dtype)
+ * from the base pointers; the input block is [5][nz+2ng][ny+2ng][nx+2ng],
+ * the output block [5][nz][ny][nx], the flux block the six sheets above.
+ * flux_off < 0 means: no boundary fluxes for this patch. Blocks of different
+ * patches must not overlap in the output and flux buffers. */
+typedef struct {
+    int32_t nx, ny, nz, ng;
+    int64_t u_in_off, u_out_off, flux_off;
+    double dx, dt;          /* cell width and time step of this patch (levels may differ) */
+} gd_patch;
+
+/* Create a context on HIP device `device` (made current). Allocates a few
+ * hundred bytes of device counters. Returns GD_E_HIP if there is no such
+ * device; then *ctx is NULL and gd_last_error(NULL) has the reason. */
+int gd_create(gd_ctx **ctx, int device);
+
+/* Release a context and its device memory (synchronises its device). */
+int gd_destroy(gd_ctx *ctx);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * gd_create on this thread when ctx is NULL). Valid until the next call. */
+const char *gd_last_error(const gd_ctx *ctx);
+
+/* Number of floor applications since the last reset (sum over calls).
+ * Synchronises the device: for tests and diagnostics only. */
+int gd_get_stats(gd_ctx *ctx, uint64_t *floor_hits);
+int gd_reset_stats(gd_ctx *ctx);
+
+/* One Godunov step of one patch (steps 1-6 above; Sec. 3 and Sec. 4 of the
+ * paper: all face fluxes of the patch computed on the device, boundary
+ * fluxes returned). nx, ny, nz >= 1; ng >= 2 for GD_GHOSTED (ignored for
+ * GD_PERIODIC). u_out must not overlap u_in. bflux may be NULL. If dt_dev is
+ * not NULL the step reads dt (a double) from that device address, e.g. as
+ * written by cfl_dt, and the dt argument is ignored. gamma > 1, dx > 0,
+ * dt >= 0 (dt is passed as double also for GD_F32 and rounded once). */
+int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                 const void *u_in, void *u_out, void *bflux,
+                 double gamma, double dx, double dt, const double *dt_dev, void *hip_stream);
+
+/* One Godunov step of every patch in a batch, in ONE persistent launch: the
+ * workgroups pull (patch, tile) items from a device work queue, so thousands
+ * of uneven patches (e.g. 8^3 .. 32^3) keep the whole GPU busy (the batch of
+ * patches that the paper's GPU ports build per level, Sec. 3 and Sec. 4).
+ * patches is a HOST array of npatch descriptors (GD_GHOSTED layout only);
+ * the library keeps a device copy and rebuilds it only when the descriptors
+ * change, so repeated calls with the same descriptors allocate nothing and
+ * may be captured into a HIP graph. If dt_dev is not NULL every patch uses
+ * the device double *dt_dev instead of patches[i].dt. bflux_base may be
+ * NULL (then every flux_off is ignored). Patches must not share output. */
+int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+                         const void *u_in_base, void *u_out_base, void *bflux_base,
+                         const double *dt_dev, double gamma, void *hip_stream);
+
+/* Reverse-mode adjoint of godunov_step for a FIXED dt (dt is not
+ * differentiated): given lam_out = dL/dU^{n+1} ([5][nz][ny][nx]) and
+ * optionally lam_bflux = dL/dbflux (boundary-flux layout, or NULL), writes
+ * lam_in = dL/dU^n in the layout of u_in: ghost-cell adjoints included for
+ * GD_GHOSTED (zero for ghosts the step does not read), contributions of
+ * wrapped neighbours folded onto the interior for GD_PERIODIC. At the kinks
+ * of the scheme (limiter switches, wave-speed min/max, HLLC region, floors)
+ * the derivative of the branch the forward step takes is used. Every
+ * element of lam_in is written exactly once (gather form, deterministic).
+ * GD_F64 only; lam_in must not overlap any input. */
+int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                         const void *u_in, const void *lam_out, const void *lam_bflux,
+                         void *lam_in, double gamma, double dx, double dt, void *hip_stream);
+
+/* CFL time step dt = cfl / max over patches p and interior cells of
+ * (|u| + |v| + |w| + 3c) / dx_p, c the sound speed of the floored primitive
+ * state (the stability bound of the unsplit scheme; the paper's codes take an
+ * adaptive time step per level, Sec. 4). Written as one double to the device
+ * address dt_dev; nothing returns to the host. patches is a HOST array;
+ * for one periodic box pass npatch = 1 and opts->bc = GD_PERIODIC with
+ * patches[0].ng = 0 and u_in_off = 0. cfl > 0. */
+int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+           const void *u_base, double gamma, double cfl, double *dt_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GODUNOV_H */

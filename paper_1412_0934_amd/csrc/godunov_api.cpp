@@ -1,0 +1,465 @@
+// C-ABI host layer of libgodunov.so: argument validation, the context (device
+// counters, cached batch tables, tuning choices) and dispatch to the kernels.
+#include "godunov.h"
+#include "godunov_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+// Message of the last failure that had no context to hold it (gd_create, or
+// an argument check of a call made with a NULL context).
+thread_local std::string g_create_error;
+
+struct BatchCache {
+    std::vector<gd_patch> host;       // descriptors the tables were built from
+    int dtype = -1, shape = -1;
+    gd::PatchDesc *d_patches = nullptr;
+    gd::WorkItem *d_items = nullptr;
+    gd::CflItem *d_cfl_items = nullptr;
+    int nitems = 0, ncfl = 0;
+    size_t cap_patches = 0, cap_items = 0, cap_cfl = 0;
+};
+
+}  // namespace
+
+struct gd_ctx {
+    int device = 0;
+    int num_cus = 0;
+    std::string err;
+    // device counters: [0] floor hits, [1] cfl max bits; queue words follow
+    unsigned long long *d_u64 = nullptr;
+    unsigned *d_u32 = nullptr;          // [0..1] work queue, [2] cfl done
+    BatchCache batch;
+    BatchCache cfl;                      // descriptor cache used by cfl_dt
+    int zlen_single = 32;
+    int shape_single = gd::TILE_16x16;
+    int shape_batched = gd::TILE_16x16;
+};
+
+namespace {
+
+int fail(gd_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+int hip_fail(gd_ctx *ctx, int e, const char *where)
+{
+    return fail(ctx, GD_E_HIP, "%s: HIP error %d (%s)", where, e,
+                hipGetErrorString((hipError_t)e));
+}
+
+int check_opts(gd_ctx *ctx, const gd_opts *o)
+{
+    if (!o) return fail(ctx, GD_E_ARG, "opts is NULL");
+    if (o->dtype != GD_F64 && o->dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", o->dtype);
+    if (o->bc != GD_GHOSTED && o->bc != GD_PERIODIC) return fail(ctx, GD_E_ARG, "bad bc %d", o->bc);
+    if (o->limiter < GD_MINMOD || o->limiter > GD_UNLIMITED)
+        return fail(ctx, GD_E_ARG, "bad limiter %d", o->limiter);
+    if (o->riemann != GD_HLLC && o->riemann != GD_HLL)
+        return fail(ctx, GD_E_ARG, "bad riemann solver %d", o->riemann);
+    if (!(o->rho_floor >= 0.0) || !(o->p_floor >= 0.0))
+        return fail(ctx, GD_E_ARG, "floors must be >= 0");
+    return GD_OK;
+}
+
+size_t elem_size(const gd_opts *o) { return o->dtype == GD_F32 ? 4 : 8; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    auto pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+int64_t in_elems(int nx, int ny, int nz, int ng, bool periodic)
+{
+    if (periodic) return 5LL * nx * ny * nz;
+    return 5LL * (nx + 2LL * ng) * (ny + 2LL * ng) * (nz + 2LL * ng);
+}
+
+int64_t flux_elems(int nx, int ny, int nz)
+{
+    return 10LL * ((int64_t)nz * ny + (int64_t)nz * nx + (int64_t)ny * nx);
+}
+
+int check_extents(gd_ctx *ctx, int nx, int ny, int nz, int ng, bool periodic)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, GD_E_ARG, "extents must be >= 1 (%d,%d,%d)", nx, ny, nz);
+    // the kernels use 16-bit tile coordinates and 32-bit plane offsets
+    if (nx > 16384 || ny > 16384 || nz > 16384) return fail(ctx, GD_E_ARG, "extent above 16384");
+    if (!periodic && ng < 2) return fail(ctx, GD_E_ARG, "ng must be >= 2 in ghosted mode (got %d)", ng);
+    if (!periodic && ng > 64) return fail(ctx, GD_E_ARG, "ng above 64");
+    int64_t gx = periodic ? nx : nx + 2LL * ng, gy = periodic ? ny : ny + 2LL * ng;
+    if (gx * gy > 0x7fffffffLL) return fail(ctx, GD_E_ARG, "plane too large");
+    return GD_OK;
+}
+
+int check_scalars(gd_ctx *ctx, double gamma, double dx, double dt)
+{
+    if (!(gamma > 1.0)) return fail(ctx, GD_E_ARG, "gamma must be > 1");
+    if (!(dx > 0.0)) return fail(ctx, GD_E_ARG, "dx must be > 0");
+    if (!(dt >= 0.0)) return fail(ctx, GD_E_ARG, "dt must be >= 0");
+    return GD_OK;
+}
+
+template <typename X>
+int ensure_capacity(gd_ctx *ctx, X **ptr, size_t *cap, size_t n)
+{
+    if (n <= *cap && *ptr) return GD_OK;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    size_t want = std::max<size_t>(n, 16);
+    hipError_t e = hipMalloc((void **)ptr, want * sizeof(X));
+    if (e != hipSuccess) return fail(ctx, GD_E_NOMEM, "hipMalloc of %zu bytes failed", want * sizeof(X));
+    *cap = want;
+    return GD_OK;
+}
+
+bool same_patches(const BatchCache &c, int npatch, const gd_patch *p)
+{
+    return (int)c.host.size() == npatch && std::memcmp(c.host.data(), p, npatch * sizeof(gd_patch)) == 0;
+}
+
+int validate_patches(gd_ctx *ctx, int npatch, const gd_patch *patches, bool periodic)
+{
+    if (npatch < 1) return fail(ctx, GD_E_ARG, "npatch must be >= 1");
+    if (!patches) return fail(ctx, GD_E_ARG, "patches is NULL");
+    for (int i = 0; i < npatch; ++i) {
+        const gd_patch &p = patches[i];
+        int r = check_extents(ctx, p.nx, p.ny, p.nz, p.ng, periodic);
+        if (r) {
+            std::string why = gd_last_error(ctx);
+            return fail(ctx, r, "patch %d: %s", i, why.c_str());
+        }
+        if (!(p.dx > 0.0)) return fail(ctx, GD_E_ARG, "patch %d: dx must be > 0", i);
+        if (!(p.dt >= 0.0)) return fail(ctx, GD_E_ARG, "patch %d: dt must be >= 0", i);
+        if (p.u_in_off < 0 || p.u_out_off < 0) return fail(ctx, GD_E_ARG, "patch %d: negative offset", i);
+    }
+    return GD_OK;
+}
+
+gd::PatchDesc to_desc(const gd_patch &p, bool periodic)
+{
+    gd::PatchDesc d{};
+    d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.ng = periodic ? 0 : p.ng;
+    d.periodic = periodic ? 1 : 0;
+    d.in_off = p.u_in_off; d.out_off = p.u_out_off; d.flux_off = p.flux_off;
+    d.dx = p.dx; d.dt = p.dt;
+    return d;
+}
+
+// z-range length of batched items by patch size: long enough to amortise the
+// two extra planes a march reads, short enough to spread a patch over
+// several workgroups.
+int batched_zlen(int nz) { return nz <= 16 ? nz : (nz <= 32 ? (nz + 1) / 2 : 16); }
+
+int build_step_tables(gd_ctx *ctx, int dtype, int shape, int npatch, const gd_patch *patches,
+                      hipStream_t s)
+{
+    BatchCache &c = ctx->batch;
+    if (c.dtype == dtype && c.shape == shape && same_patches(c, npatch, patches)) return GD_OK;
+    const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
+    std::vector<gd::PatchDesc> desc(npatch);
+    std::vector<gd::WorkItem> items;
+    std::vector<std::pair<int64_t, int>> order;     // (cells, patch): largest first
+    for (int i = 0; i < npatch; ++i) {
+        desc[i] = to_desc(patches[i], false);
+        order.push_back({-(int64_t)patches[i].nx * patches[i].ny * patches[i].nz, i});
+    }
+    std::stable_sort(order.begin(), order.end());
+    for (auto &o : order) {
+        const gd_patch &p = patches[o.second];
+        const int zl = batched_zlen(p.nz);
+        for (int z0 = 0; z0 < p.nz; z0 += zl)
+            for (int y0 = 0; y0 < p.ny; y0 += TY)
+                for (int x0 = 0; x0 < p.nx; x0 += TX) {
+                    gd::WorkItem w{};
+                    w.patch = o.second;
+                    w.x0 = (int16_t)x0; w.y0 = (int16_t)y0;
+                    w.z0 = (int16_t)z0; w.z1 = (int16_t)std::min(z0 + zl, p.nz);
+                    w.shape = (int16_t)shape;
+                    items.push_back(w);
+                }
+    }
+    if (items.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many work items");
+    int r;
+    if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
+    if ((r = ensure_capacity(ctx, &c.d_items, &c.cap_items, items.size()))) return r;
+    // The tables are written before any kernel that reads them: a synchronous
+    // copy keeps the host vectors' lifetime out of the stream.
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_items, items.data(), items.size() * sizeof(gd::WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of batch tables");
+    c.host.assign(patches, patches + npatch);
+    c.nitems = (int)items.size();
+    c.dtype = dtype;
+    c.shape = shape;
+    return GD_OK;
+}
+
+int build_cfl_tables(gd_ctx *ctx, bool periodic, int npatch, const gd_patch *patches, hipStream_t s)
+{
+    BatchCache &c = ctx->cfl;
+    int tag = periodic ? 1 : 0;
+    if (c.dtype == tag && same_patches(c, npatch, patches)) return GD_OK;
+    std::vector<gd::PatchDesc> desc(npatch);
+    std::vector<gd::CflItem> items;
+    for (int i = 0; i < npatch; ++i) {
+        const gd_patch &p = patches[i];
+        desc[i] = to_desc(p, periodic);
+        // about 2048 cells per item
+        int rows = std::max(1, std::min(p.ny, 2048 / std::max(1, p.nx)));
+        for (int k = 0; k < p.nz; ++k)
+            for (int j0 = 0; j0 < p.ny; j0 += rows)
+                items.push_back(gd::CflItem{ i, k, j0, std::min(rows, p.ny - j0) });
+    }
+    if (items.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many cfl items");
+    int r;
+    if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
+    if ((r = ensure_capacity(ctx, &c.d_cfl_items, &c.cap_cfl, items.size()))) return r;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_cfl_items, items.data(), items.size() * sizeof(gd::CflItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of cfl tables");
+    c.host.assign(patches, patches + npatch);
+    c.ncfl = (int)items.size();
+    c.dtype = tag;
+    return GD_OK;
+}
+
+int set_device(gd_ctx *ctx)
+{
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gd_create(gd_ctx **out, int device)
+{
+    if (!out) return fail(nullptr, GD_E_ARG, "ctx pointer is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) return fail(nullptr, GD_E_HIP, "no HIP device available");
+    if (device < 0 || device >= n) return fail(nullptr, GD_E_ARG, "device %d out of range [0,%d)", device, n);
+    if ((e = hipSetDevice(device)) != hipSuccess) return fail(nullptr, GD_E_HIP, "hipSetDevice(%d) failed", device);
+    gd_ctx *ctx = new gd_ctx();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    if (ctx->num_cus < 1) ctx->num_cus = 256;
+    e = hipMalloc((void **)&ctx->d_u64, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_u32, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(ctx->d_u32, 0, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        gd_destroy(ctx);
+        return fail(nullptr, GD_E_NOMEM, "device scratch allocation failed");
+    }
+    *out = ctx;
+    return GD_OK;
+}
+
+int gd_destroy(gd_ctx *ctx)
+{
+    if (!ctx) return GD_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (BatchCache *c : { &ctx->batch, &ctx->cfl }) {
+        if (c->d_patches) (void)hipFree(c->d_patches);
+        if (c->d_items) (void)hipFree(c->d_items);
+        if (c->d_cfl_items) (void)hipFree(c->d_cfl_items);
+    }
+    if (ctx->d_u64) (void)hipFree(ctx->d_u64);
+    if (ctx->d_u32) (void)hipFree(ctx->d_u32);
+    delete ctx;
+    return GD_OK;
+}
+
+const char *gd_last_error(const gd_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int gd_get_stats(gd_ctx *ctx, uint64_t *floor_hits)
+{
+    if (!ctx || !floor_hits) return fail(ctx, GD_E_ARG, "NULL argument");
+    int r = set_device(ctx);
+    if (r) return r;
+    unsigned long long h = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&h, ctx->d_u64, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gd_get_stats");
+    *floor_hits = h;
+    return GD_OK;
+}
+
+int gd_reset_stats(gd_ctx *ctx)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "NULL ctx");
+    int r = set_device(ctx);
+    if (r) return r;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "gd_reset_stats");
+    return GD_OK;
+}
+
+int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                 const void *u_in, void *u_out, void *bflux, double gamma, double dx, double dt,
+                 const double *dt_dev, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    const bool periodic = opts->bc == GD_PERIODIC;
+    if ((r = check_extents(ctx, nx, ny, nz, ng, periodic))) return r;
+    if ((r = check_scalars(ctx, gamma, dx, dt_dev ? 0.0 : dt))) return r;
+    if (!u_in || !u_out) return fail(ctx, GD_E_ARG, "u_in and u_out must not be NULL");
+    const size_t es = elem_size(opts);
+    const size_t nin = (size_t)in_elems(nx, ny, nz, ng, periodic) * es;
+    const size_t nout = 5ull * nx * ny * nz * es;
+    const size_t nfl = (size_t)flux_elems(nx, ny, nz) * es;
+    if (overlap(u_in, nin, u_out, nout)) return fail(ctx, GD_E_ARG, "u_out overlaps u_in");
+    if (bflux && (overlap(bflux, nfl, u_in, nin) || overlap(bflux, nfl, u_out, nout)))
+        return fail(ctx, GD_E_ARG, "bflux overlaps u_in or u_out");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+
+    gd::PatchDesc P{};
+    P.nx = nx; P.ny = ny; P.nz = nz; P.ng = periodic ? 0 : ng; P.periodic = periodic;
+    P.in_off = 0; P.out_off = 0; P.flux_off = bflux ? 0 : -1;
+    P.dx = dx; P.dt = dt;
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann, ctx->shape_single, P, u_in,
+                            u_out, bflux, dt_dev, sc, ctx->d_u64, ctx->zlen_single,
+                            (hipStream_t)hip_stream);
+    if (e) return hip_fail(ctx, e, "godunov_step launch");
+    return GD_OK;
+}
+
+int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+                         const void *u_in_base, void *u_out_base, void *bflux_base,
+                         const double *dt_dev, double gamma, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if (opts->bc != GD_GHOSTED) return fail(ctx, GD_E_UNSUPPORTED, "batched calls take ghosted patches only");
+    if ((r = validate_patches(ctx, npatch, patches, false))) return r;
+    if (!(gamma > 1.0)) return fail(ctx, GD_E_ARG, "gamma must be > 1");
+    if (!u_in_base || !u_out_base) return fail(ctx, GD_E_ARG, "u_in_base and u_out_base must not be NULL");
+    // extents of the three buffers, for the overlap check
+    int64_t in_end = 0, out_end = 0, fl_end = 0;
+    for (int i = 0; i < npatch; ++i) {
+        const gd_patch &p = patches[i];
+        in_end = std::max<int64_t>(in_end, p.u_in_off + in_elems(p.nx, p.ny, p.nz, p.ng, false));
+        out_end = std::max<int64_t>(out_end, p.u_out_off + (int64_t)5 * p.nx * p.ny * p.nz);
+        if (bflux_base && p.flux_off >= 0) fl_end = std::max<int64_t>(fl_end, p.flux_off + flux_elems(p.nx, p.ny, p.nz));
+    }
+    const size_t es = elem_size(opts);
+    if (overlap(u_in_base, in_end * es, u_out_base, out_end * es))
+        return fail(ctx, GD_E_ARG, "u_out_base range overlaps u_in_base range");
+    if (bflux_base && fl_end > 0 && (overlap(bflux_base, fl_end * es, u_in_base, in_end * es) ||
+                                     overlap(bflux_base, fl_end * es, u_out_base, out_end * es)))
+        return fail(ctx, GD_E_ARG, "bflux range overlaps u_in or u_out");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((r = build_step_tables(ctx, opts->dtype, ctx->shape_batched, npatch, patches, s))) return r;
+    const BatchCache &c = ctx->batch;
+    int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, c.shape, ctx->device);
+    int grid = std::min(c.nitems, per_cu * ctx->num_cus);
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    int e = gd::launch_step_batched(opts->dtype, opts->limiter, opts->riemann, c.shape, c.d_patches,
+                                    c.d_items, c.nitems, u_in_base, u_out_base, bflux_base, dt_dev,
+                                    sc, ctx->d_u64, ctx->d_u32, std::max(grid, 1), s);
+    if (e) return hip_fail(ctx, e, "godunov_step_batched launch");
+    return GD_OK;
+}
+
+int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+           const void *u_base, double gamma, double cfl, double *dt_dev, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    const bool periodic = opts->bc == GD_PERIODIC;
+    if ((r = validate_patches(ctx, npatch, patches, periodic))) return r;
+    if (!(gamma > 1.0)) return fail(ctx, GD_E_ARG, "gamma must be > 1");
+    if (!(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
+    if (!u_base || !dt_dev) return fail(ctx, GD_E_ARG, "u_base and dt_dev must not be NULL");
+    if (periodic && npatch != 1) return fail(ctx, GD_E_ARG, "periodic mode takes exactly one patch");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    hipStream_t s = (hipStream_t)hip_stream;
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    int e;
+    if (npatch == 1) {
+        gd::PatchDesc P = to_desc(patches[0], periodic);
+        e = gd::launch_cfl_single(opts->dtype, P, u_base, sc, cfl, dt_dev, ctx->d_u64 + 1,
+                                  ctx->d_u32 + 2, s);
+    } else {
+        if ((r = build_cfl_tables(ctx, periodic, npatch, patches, s))) return r;
+        const BatchCache &c = ctx->cfl;
+        int grid = std::min(c.ncfl, 8 * ctx->num_cus);
+        e = gd::launch_cfl(opts->dtype, c.d_patches, c.d_cfl_items, c.ncfl, u_base, sc, cfl, dt_dev,
+                           ctx->d_u64 + 1, ctx->d_u32 + 2, std::max(grid, 1), s);
+    }
+    if (e) return hip_fail(ctx, e, "cfl_dt launch");
+    return GD_OK;
+}
+
+int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                         const void *u_in, const void *lam_out, const void *lam_bflux,
+                         void *lam_in, double gamma, double dx, double dt, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if (opts->dtype != GD_F64) return fail(ctx, GD_E_UNSUPPORTED, "the adjoint is FP64 only");
+    const bool periodic = opts->bc == GD_PERIODIC;
+    if ((r = check_extents(ctx, nx, ny, nz, ng, periodic))) return r;
+    if ((r = check_scalars(ctx, gamma, dx, dt))) return r;
+    if (!u_in || !lam_out || !lam_in) return fail(ctx, GD_E_ARG, "u_in, lam_out and lam_in must not be NULL");
+    const size_t nin = (size_t)in_elems(nx, ny, nz, ng, periodic) * 8;
+    const size_t nout = 5ull * nx * ny * nz * 8;
+    const size_t nfl = (size_t)flux_elems(nx, ny, nz) * 8;
+    if (overlap(lam_in, nin, u_in, nin) || overlap(lam_in, nin, lam_out, nout) ||
+        (lam_bflux && overlap(lam_in, nin, lam_bflux, nfl)))
+        return fail(ctx, GD_E_ARG, "lam_in overlaps an input");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    gd::PatchDesc P{};
+    P.nx = nx; P.ny = ny; P.nz = nz; P.ng = periodic ? 0 : ng; P.periodic = periodic;
+    P.flux_off = lam_bflux ? 0 : -1;
+    P.dx = dx; P.dt = dt;
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    int e = gd::launch_adjoint(opts->limiter, opts->riemann, P, (const double *)u_in,
+                               (const double *)lam_out, (const double *)lam_bflux, (double *)lam_in,
+                               sc, dt, (hipStream_t)hip_stream);
+    if (e == (int)hipErrorNotSupported) return fail(ctx, GD_E_UNSUPPORTED, "adjoint not available");
+    if (e) return hip_fail(ctx, e, "godunov_step_adjoint launch");
+    return GD_OK;
+}
+
+}  // extern "C"

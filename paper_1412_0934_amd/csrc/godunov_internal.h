@@ -1,0 +1,72 @@
+// Internal interface between the C-ABI host layer (godunov_api.cpp) and the
+// gfx950 kernels (godunov_kernels.hip). Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gd {
+
+// Device-side description of one patch. Offsets are in elements of the call's
+// dtype. For a periodic box ng = 0 and the input has the output's shape.
+struct PatchDesc {
+    int32_t nx, ny, nz, ng;
+    int32_t periodic;
+    int32_t pad_;
+    int64_t in_off, out_off, flux_off;   // flux_off < 0: no boundary fluxes
+    double dx, dt;
+};
+
+// One unit of work of the forward step: an x-y tile of a patch and the
+// z-range [z0, z1) that the workgroup marches through.
+struct WorkItem {
+    int32_t patch;
+    int16_t x0, y0;
+    int16_t z0, z1;
+    int16_t shape;       // index of the tile shape (kernel variant) to use
+    int16_t pad_;
+};
+
+// Tile shapes the forward kernels are instantiated for (interior columns
+// TX x TY of one workgroup).
+enum TileShape : int { TILE_16x16 = 0, TILE_8x8 = 1, TILE_32x8 = 2, NUM_TILE_SHAPES = 3 };
+int tile_tx(int shape);
+int tile_ty(int shape);
+
+struct Scalars {
+    double gamma, rho_floor, p_floor;
+};
+
+// Launchers. Return 0 or a hipError_t value.
+int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
+                const void *u_in, void *u_out, void *bflux, const double *dt_dev,
+                const Scalars &sc, unsigned long long *hits, int zlen, hipStream_t s);
+
+int launch_step_batched(int dtype, int limiter, int riemann, int shape,
+                        const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
+                        const void *u_in, void *u_out, void *bflux, const double *dt_dev,
+                        const Scalars &sc, unsigned long long *hits, unsigned *d_queue,
+                        int grid, hipStream_t s);
+
+// Work item of the CFL reduction: rows [j0, j0+nrow) of plane k of a patch.
+struct CflItem {
+    int32_t patch;
+    int32_t k;
+    int32_t j0, nrow;
+};
+
+int launch_cfl(int dtype, const PatchDesc *d_patches, const CflItem *d_items, int nitems,
+               const void *u, const Scalars &sc, double cfl, double *dt_out,
+               unsigned long long *smax_bits, unsigned *done, int grid, hipStream_t s);
+
+int launch_cfl_single(int dtype, const PatchDesc &P, const void *u, const Scalars &sc,
+                      double cfl, double *dt_out, unsigned long long *smax_bits,
+                      unsigned *done, hipStream_t s);
+
+int launch_adjoint(int limiter, int riemann, const PatchDesc &P, const double *u_in,
+                   const double *lam_out, const double *lam_bflux, double *lam_in,
+                   const Scalars &sc, double dt, hipStream_t s);
+
+int max_resident_blocks(int dtype, int limiter, int riemann, int shape, int device);
+
+}  // namespace gd

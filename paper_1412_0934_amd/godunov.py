@@ -1,0 +1,327 @@
+"""Python binding of libgodunov.so (ctypes), plus a differentiable rollout.
+
+Argument marshalling only: every step of the scheme runs in the library's HIP
+kernels. PyTorch supplies the device memory (tensors) and the stream (the
+current torch stream). There is no CPU fallback: if the library is not built
+or no GPU is present, the calls raise.
+
+Entry points (same names as the C ABI, see include/godunov.h):
+    step(u, gamma, dx, dt)            one patch (ghosted or periodic)
+    step_batched(...)                 many ghost-zoned patches, one launch
+    step_adjoint(u, lam_out, ...)     reverse mode of step for a fixed dt
+    cfl_dt(u, gamma, dx, cfl)         CFL time step as a device scalar
+    GodunovRollout                    torch.autograd.Function over K steps
+                                      with checkpointed recomputation
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgodunov.so")
+
+GD_OK, GD_E_ARG, GD_E_HIP, GD_E_NOMEM, GD_E_UNSUPPORTED = 0, -1, -2, -3, -4
+DTYPES = {torch.float64: 0, torch.float32: 1}
+LIMITERS = {"minmod": 0, "mc": 1, "unlimited": 2, "none": 2}
+RIEMANN = {"hllc": 0, "hll": 1}
+RHO_FLOOR = 1e-10
+P_FLOOR = 1e-10
+
+
+class GodunovError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+class gd_opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("bc", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("riemann", ctypes.c_int32), ("rho_floor", ctypes.c_double),
+                ("p_floor", ctypes.c_double)]
+
+
+class gd_patch(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ng", ctypes.c_int32), ("u_in_off", ctypes.c_int64),
+                ("u_out_off", ctypes.c_int64), ("flux_off", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+PATCH_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("ng", "<i4"),
+                        ("u_in_off", "<i8"), ("u_out_off", "<i8"), ("flux_off", "<i8"),
+                        ("dx", "<f8"), ("dt", "<f8")], align=True)
+assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
+
+EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
+           "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt")
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgodunov.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        P = ctypes.POINTER
+        lib.gd_create.argtypes = [P(vp), i32]
+        lib.gd_destroy.argtypes = [vp]
+        lib.gd_last_error.argtypes = [vp]
+        lib.gd_last_error.restype = ctypes.c_char_p
+        lib.gd_get_stats.argtypes = [vp, P(ctypes.c_uint64)]
+        lib.gd_reset_stats.argtypes = [vp]
+        lib.godunov_step.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, vp, dbl, dbl, dbl,
+                                     vp, vp]
+        lib.godunov_step_batched.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, vp, dbl, vp]
+        lib.godunov_step_adjoint.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, vp, vp,
+                                             dbl, dbl, dbl, vp]
+        lib.cfl_dt.argtypes = [vp, P(gd_opts), i32, vp, vp, dbl, dbl, vp, vp]
+        for name in EXPORTS:
+            if name != "gd_last_error":
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+class Context:
+    """A gd_ctx bound to one device. One per (thread, device) via `context()`."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        r = self.lib.gd_create(ctypes.byref(h), device)
+        if r != GD_OK:
+            raise GodunovError(r, self.lib.gd_last_error(None).decode())
+        self.handle = h
+
+    def check(self, r: int) -> None:
+        if r != GD_OK:
+            raise GodunovError(r, self.lib.gd_last_error(self.handle).decode())
+
+    def floor_hits(self) -> int:
+        v = ctypes.c_uint64()
+        self.check(self.lib.gd_get_stats(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    def reset_stats(self) -> None:
+        self.check(self.lib.gd_reset_stats(self.handle))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and self.handle.value:
+                self.lib.gd_destroy(self.handle)
+        except Exception:
+            pass
+
+
+_contexts: dict = {}
+
+
+def context(device=None) -> Context:
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the Godunov library has no CPU path")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    key = (threading.get_ident(), dev)
+    if key not in _contexts:
+        _contexts[key] = Context(dev)
+    return _contexts[key]
+
+
+def _opts(dtype, periodic, limiter, riemann, rho_floor, p_floor) -> gd_opts:
+    if dtype not in DTYPES:
+        raise TypeError(f"unsupported dtype {dtype}")
+    return gd_opts(DTYPES[dtype], 1 if periodic else 0, LIMITERS[limiter], RIEMANN[riemann],
+                   float(rho_floor), float(p_floor))
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+
+
+def bflux_size(nx, ny, nz) -> int:
+    return 10 * (nz * ny + nz * nx + ny * nx)
+
+
+def interior_shape(u, ng, periodic):
+    if u.dim() != 4 or u.shape[0] != 5:
+        raise ValueError(f"state must have shape (5, z, y, x), got {tuple(u.shape)}")
+    gz, gy, gx = u.shape[1:]
+    if periodic:
+        return gx, gy, gz
+    return gx - 2 * ng, gy - 2 * ng, gz - 2 * ng
+
+
+def step(u, gamma, dx, dt=None, *, dt_dev=None, ng=2, periodic=False, limiter="minmod",
+         riemann="hllc", want_bflux=True, out=None, bflux=None, rho_floor=RHO_FLOOR,
+         p_floor=P_FLOOR, stream=None):
+    """One Godunov step of one patch. Returns (u_new [5,nz,ny,nx], bflux or None)."""
+    _check_tensor(u, "u")
+    nx, ny, nz = interior_shape(u, ng, periodic)
+    if out is None:
+        out = torch.empty((5, nz, ny, nx), dtype=u.dtype, device=u.device)
+    _check_tensor(out, "out", u.dtype)
+    if want_bflux and bflux is None:
+        bflux = torch.empty(bflux_size(nx, ny, nz), dtype=u.dtype, device=u.device)
+    if not want_bflux:
+        bflux = None
+    if dt_dev is not None:
+        _check_tensor(dt_dev, "dt_dev", torch.float64)
+    if dt is None and dt_dev is None:
+        raise ValueError("give dt or dt_dev")
+    ctx = context(u.device.index)
+    o = _opts(u.dtype, periodic, limiter, riemann, rho_floor, p_floor)
+    ctx.check(ctx.lib.godunov_step(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u), _ptr(out),
+                                   _ptr(bflux), float(gamma), float(dx),
+                                   float(dt if dt is not None else 0.0), _ptr(dt_dev),
+                                   _stream(stream)))
+    return out, bflux
+
+
+def cfl_dt(u, gamma, dx, cfl=0.5, *, ng=2, periodic=False, out=None, rho_floor=RHO_FLOOR,
+           p_floor=P_FLOOR, stream=None):
+    """CFL step of one patch as a 1-element float64 device tensor."""
+    _check_tensor(u, "u")
+    nx, ny, nz = interior_shape(u, ng, periodic)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=u.device)
+    _check_tensor(out, "out", torch.float64)
+    ctx = context(u.device.index)
+    o = _opts(u.dtype, periodic, "minmod", "hllc", rho_floor, p_floor)
+    desc = np.zeros(1, dtype=PATCH_DTYPE)
+    desc[0] = (nx, ny, nz, 0 if periodic else ng, 0, 0, -1, float(dx), 0.0)
+    ctx.check(ctx.lib.cfl_dt(ctx.handle, ctypes.byref(o), 1, desc.ctypes.data, _ptr(u),
+                             float(gamma), float(cfl), _ptr(out), _stream(stream)))
+    return out
+
+
+def patch_table(dims, ng, u_in_off, u_out_off, flux_off, dx, dt=0.0) -> np.ndarray:
+    """Structured array of gd_patch records (host memory)."""
+    dims = np.asarray(dims)
+    n = len(dims)
+    t = np.zeros(n, dtype=PATCH_DTYPE)
+    t["nx"], t["ny"], t["nz"] = dims[:, 0], dims[:, 1], dims[:, 2]
+    t["ng"] = ng
+    t["u_in_off"], t["u_out_off"] = u_in_off, u_out_off
+    t["flux_off"] = flux_off
+    t["dx"] = dx
+    t["dt"] = dt
+    return t
+
+
+def step_batched(u_in, table, gamma, *, out, bflux=None, dt_dev=None, limiter="minmod",
+                 riemann="hllc", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None):
+    """One step of every patch in `table` (see patch_table), one launch."""
+    _check_tensor(u_in, "u_in")
+    _check_tensor(out, "out", u_in.dtype)
+    if bflux is not None:
+        _check_tensor(bflux, "bflux", u_in.dtype)
+    if dt_dev is not None:
+        _check_tensor(dt_dev, "dt_dev", torch.float64)
+    table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    ctx = context(u_in.device.index)
+    o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
+    ctx.check(ctx.lib.godunov_step_batched(ctx.handle, ctypes.byref(o), len(table),
+                                           table.ctypes.data, _ptr(u_in), _ptr(out), _ptr(bflux),
+                                           _ptr(dt_dev), float(gamma), _stream(stream)))
+    return out, bflux
+
+
+def cfl_dt_batched(u_in, table, gamma, cfl=0.5, *, out=None, rho_floor=RHO_FLOOR,
+                   p_floor=P_FLOOR, stream=None):
+    _check_tensor(u_in, "u_in")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=u_in.device)
+    table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    ctx = context(u_in.device.index)
+    o = _opts(u_in.dtype, False, "minmod", "hllc", rho_floor, p_floor)
+    ctx.check(ctx.lib.cfl_dt(ctx.handle, ctypes.byref(o), len(table), table.ctypes.data,
+                             _ptr(u_in), float(gamma), float(cfl), _ptr(out), _stream(stream)))
+    return out
+
+
+def step_adjoint(u, lam_out, gamma, dx, dt, *, lam_bflux=None, ng=2, periodic=False,
+                 limiter="minmod", riemann="hllc", out=None, rho_floor=RHO_FLOOR,
+                 p_floor=P_FLOOR, stream=None):
+    """dL/dU^n of one step (fixed dt) from dL/dU^{n+1} (and dL/dbflux)."""
+    _check_tensor(u, "u", torch.float64)
+    _check_tensor(lam_out, "lam_out", torch.float64)
+    nx, ny, nz = interior_shape(u, ng, periodic)
+    if tuple(lam_out.shape) != (5, nz, ny, nx):
+        raise ValueError("lam_out has the wrong shape")
+    if lam_bflux is not None:
+        _check_tensor(lam_bflux, "lam_bflux", torch.float64)
+    if out is None:
+        out = torch.empty_like(u)
+    ctx = context(u.device.index)
+    o = _opts(torch.float64, periodic, limiter, riemann, rho_floor, p_floor)
+    ctx.check(ctx.lib.godunov_step_adjoint(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u),
+                                           _ptr(lam_out), _ptr(lam_bflux), _ptr(out),
+                                           float(gamma), float(dx), float(dt), _stream(stream)))
+    return out
+
+
+class GodunovRollout(torch.autograd.Function):
+    """K periodic steps with a fixed dt, differentiable with respect to the
+    initial state. The forward keeps every `every`-th state; the backward
+    recomputes each segment from its checkpoint and runs the adjoint steps
+    in reverse (checkpointed recomputation)."""
+
+    @staticmethod
+    def forward(ctx, u0, gamma, dx, dt, nsteps, every, limiter, riemann):
+        u = u0.contiguous()
+        checkpoints = [u]
+        for k in range(nsteps):
+            u, _ = step(u, gamma, dx, dt, periodic=True, limiter=limiter, riemann=riemann,
+                        want_bflux=False)
+            if (k + 1) % every == 0 and k + 1 < nsteps:
+                checkpoints.append(u)
+        ctx.save_for_backward(*checkpoints)
+        ctx.args = (gamma, dx, dt, nsteps, every, limiter, riemann)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gamma, dx, dt, nsteps, every, limiter, riemann = ctx.args
+        checkpoints = ctx.saved_tensors
+        lam = grad_out.contiguous()
+        for seg in reversed(range(len(checkpoints))):
+            start = seg * every
+            stop = min(start + every, nsteps)
+            states = [checkpoints[seg]]
+            for _ in range(start, stop - 1):
+                states.append(step(states[-1], gamma, dx, dt, periodic=True, limiter=limiter,
+                                   riemann=riemann, want_bflux=False)[0])
+            for s in reversed(states):
+                lam = step_adjoint(s, lam, gamma, dx, dt, periodic=True, limiter=limiter,
+                                   riemann=riemann)
+        return lam, None, None, None, None, None, None, None
+
+
+def rollout(u0, gamma, dx, dt, nsteps, every=5, limiter="minmod", riemann="hllc"):
+    return GodunovRollout.apply(u0, gamma, dx, dt, nsteps, every, limiter, riemann)

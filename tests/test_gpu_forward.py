@@ -1,0 +1,225 @@
+"""GPU forward step and CFL time step against the CPU oracle, through the C ABI.
+
+Parity bar: per-variable max |gpu - oracle| / max |oracle| <= 1e-12 in FP64 and
+<= 1e-5 for FP32 against the FP64 oracle (one step), on seeded inputs that
+span several tiles, ragged tile tails and z segments. Invariants that hold
+bitwise on the GPU as well (free stream, 1-D reduction, unread corners) are
+checked exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_norm_err, say
+from paper_1412_0934_amd import inputs
+
+pytestmark = pytest.mark.gpu
+G = 5.0 / 3.0
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module")
+def gd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0934_amd import godunov
+    return godunov
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+# ------------------------------------------------------------------ single patch
+
+
+def test_sod_patch_32_fp64_and_fp32(gd):
+    """32^3 + 2 ghosts, Sod jump with 1% noise, CFL 0.5, minmod + HLLC."""
+    import torch
+    u, dx = inputs.sod_patch(32, noise=0.01, seed=0)
+    dt = oracle.cfl_dt(u, G, dx, 0.5)
+    ref, rflux, _ = oracle.step(u, G, dx, dt)
+    say("sod32 fp64")
+    out, flux = gd.step(dev(u), G, dx, dt)
+    assert rel_norm_err(host(out), ref) <= TOL64
+    assert rel_norm_err(host(flux), rflux) <= TOL64
+    say("sod32 fp32")
+    out, flux = gd.step(dev(u, torch.float32), G, dx, dt)
+    assert rel_norm_err(host(out), ref) <= TOL32
+    assert rel_norm_err(host(flux), rflux) <= TOL32
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (17, 16, 3), (33, 20, 18), (1, 1, 1), (40, 3, 37),
+                                   (16, 16, 40)])
+@pytest.mark.parametrize("lim", ["minmod", "mc", "none"])
+@pytest.mark.parametrize("rs", ["hllc", "hll"])
+def test_random_ghosted_patches(gd, shape, lim, rs):
+    nx, ny, nz = shape
+    u = inputs.random_patch(nx, ny, nz, seed=nx * 131 + ny * 7 + nz)
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx)
+    ref, rflux, _ = oracle.step(u, G, dx, dt, limiter=lim, riemann=rs)
+    say("ghosted", shape, lim, rs)
+    out, flux = gd.step(dev(u), G, dx, dt, limiter=lim, riemann=rs)
+    assert rel_norm_err(host(out), ref) <= TOL64
+    assert rel_norm_err(host(flux), rflux) <= TOL64
+
+
+@pytest.mark.parametrize("n", [8, 24, 40])
+@pytest.mark.parametrize("lim", ["minmod", "mc"])
+def test_periodic_box(gd, n, lim):
+    u = inputs.turbulent_box(n, mach=2.0)
+    dx = 1 / n
+    dt = oracle.cfl_dt(u, G, dx, periodic=True)
+    ref, rflux, _ = oracle.step(u, G, dx, dt, periodic=True, limiter=lim)
+    say("periodic", n, lim)
+    out, flux = gd.step(dev(u), G, dx, dt, periodic=True, limiter=lim)
+    assert rel_norm_err(host(out), ref) <= TOL64
+    assert rel_norm_err(host(flux), rflux) <= TOL64
+
+
+def test_periodic_box_fp32(gd):
+    import torch
+    u = inputs.turbulent_box(32, mach=2.0)
+    dx = 1 / 32
+    dt = oracle.cfl_dt(u, G, dx, periodic=True)
+    ref, _, _ = oracle.step(u, G, dx, dt, periodic=True)
+    say("periodic fp32 32")
+    out, _ = gd.step(dev(u, torch.float32), G, dx, dt, periodic=True)
+    assert rel_norm_err(host(out), ref) <= TOL32
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_free_stream_bitwise(gd, periodic):
+    import torch
+    one = np.ones((9, 10, 11))
+    U = inputs.conserved(1.3 * one, 0.4 * one, -0.7 * one, 0.25 * one, 0.8 * one, G)
+    u = U if periodic else inputs.outflow_fill(U, 2)
+    for dtype in (torch.float64, torch.float32):
+        say("free stream", periodic, dtype)
+        ud = dev(u, dtype)
+        out, _ = gd.step(ud, G, 0.01, 0.002, periodic=periodic)
+        expect = U if dtype == torch.float64 else U.astype(np.float32).astype(np.float64)
+        assert np.array_equal(host(out), expect)
+
+
+def test_one_dimensional_reduction_bitwise(gd):
+    n = 24
+    x = (np.arange(n) + 0.5) / n
+    rho = 1.0 + 0.5 * (x > 0.4) + 0.1 * np.sin(6 * x)
+    p = 1.0 + 0.8 * (x < 0.6)
+    ux = 0.3 * np.cos(5 * x)
+    shape = (20, 18, n)
+    zero = np.zeros(shape)
+    U = inputs.conserved(np.broadcast_to(rho, shape), np.broadcast_to(ux, shape), zero, zero,
+                         np.broadcast_to(p, shape), G)
+    say("1-d reduction")
+    out, _ = gd.step(dev(inputs.outflow_fill(U, 2)), G, 1 / n, 0.004)
+    o = host(out)
+    for v in range(5):
+        assert np.array_equal(o[v], np.broadcast_to(o[v, :1, :1, :], o[v].shape))
+    assert np.all(o[2] == 0.0) and np.all(o[3] == 0.0)
+
+
+def test_corner_ghosts_are_never_read(gd):
+    u = inputs.random_patch(19, 17, 10, seed=9)
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx)
+    say("poisoned corners reference")
+    ref, rflux = gd.step(dev(u), G, dx, dt)
+    ref, rflux = host(ref), host(rflux)
+    gz, gy, gx = u.shape[1:]
+    k, j, i = np.meshgrid(np.arange(gz), np.arange(gy), np.arange(gx), indexing="ij")
+    depth = [np.maximum(np.maximum(2 - c, c - (n - 3)), 0) for c, n in ((i, gx), (j, gy), (k, gz))]
+    nout = sum((d > 0).astype(int) for d in depth)
+    dmax = np.maximum(np.maximum(depth[0], depth[1]), depth[2])
+    unread = (nout == 3) | ((nout == 2) & (dmax > 1))
+    poisoned = u.copy()
+    poisoned[:, unread] = np.nan
+    say("poisoned corners")
+    out, flux = gd.step(dev(poisoned), G, dx, dt)
+    assert np.array_equal(host(out), ref) and np.array_equal(host(flux), rflux)
+
+
+def test_run_twice_is_bitwise_deterministic(gd):
+    u = inputs.random_patch(30, 29, 28, seed=12)
+    say("determinism")
+    a, fa = gd.step(dev(u), G, 1 / 64, 1e-3)
+    b, fb = gd.step(dev(u), G, 1 / 64, 1e-3)
+    assert np.array_equal(host(a), host(b)) and np.array_equal(host(fa), host(fb))
+
+
+def test_floors_are_counted(gd):
+    u = inputs.random_patch(12, 12, 12, seed=1)
+    ctx = gd.context()
+    ctx.reset_stats()
+    say("floors: clean")
+    gd.step(dev(u), G, 1 / 64, 1e-4)
+    assert ctx.floor_hits() == 0
+    u[0, 6, 6, 6] = -0.5
+    say("floors: injected")
+    out, _ = gd.step(dev(u), G, 1 / 64, 1e-4)
+    assert ctx.floor_hits() > 0
+    assert np.all(np.isfinite(host(out)))
+    ref, _, _ = oracle.step(u, G, 1 / 64, 1e-4)
+    # the floored cell carries u = m / rho_floor ~ 1e10, which magnifies the
+    # rounding-order differences of its neighbours' fluxes by about 1e2
+    assert rel_norm_err(host(out), ref) <= 1e-10
+
+
+def test_dt_from_device_scalar(gd):
+    import torch
+    u = inputs.random_patch(20, 12, 9, seed=3)
+    dt = oracle.cfl_dt(u, G, 1 / 64)
+    say("dt_dev")
+    a, _ = gd.step(dev(u), G, 1 / 64, dt)
+    b, _ = gd.step(dev(u), G, 1 / 64, dt_dev=torch.tensor([dt], dtype=torch.float64, device="cuda"))
+    assert np.array_equal(host(a), host(b))
+
+
+# ------------------------------------------------------------------ CFL
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_cfl_dt_parity(gd, periodic):
+    import torch
+    if periodic:
+        u, dx = inputs.turbulent_box(48, mach=2.0), 1 / 48
+    else:
+        u, dx = inputs.sod_patch(32, noise=0.01)
+    ref = oracle.cfl_dt(u, G, dx, 0.5, periodic=periodic)
+    for dtype, tol in ((torch.float64, 1e-14), (torch.float32, 1e-6)):
+        say("cfl", periodic, dtype)
+        got = float(host(gd.cfl_dt(dev(u, dtype), G, dx, 0.5, periodic=periodic))[0])
+        assert abs(got - ref) <= tol * ref
+    # the accumulators reset themselves: a second call gives the same value
+    got2 = float(host(gd.cfl_dt(dev(u), G, dx, 0.5, periodic=periodic))[0])
+    assert abs(got2 - ref) <= 1e-14 * ref
+
+
+def test_ten_step_periodic_rollout_with_device_dt(gd):
+    """Ten steps on a 64^3 Mach-2 box, dt from cfl_dt on the device each step,
+    against the oracle's own ten-step rollout (its own dt each step)."""
+    import torch
+    n = 64
+    u = inputs.turbulent_box(n, mach=2.0)
+    dx = 1 / n
+    ref = u
+    for _ in range(10):
+        ref = oracle.step(ref, G, dx, oracle.cfl_dt(ref, G, dx, periodic=True), periodic=True)[0]
+    say("10-step rollout 64^3")
+    ud = dev(u)
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        gd.cfl_dt(ud, G, dx, 0.5, periodic=True, out=dt_dev)
+        ud, _ = gd.step(ud, G, dx, dt_dev=dt_dev, periodic=True, want_bflux=False)
+    assert rel_norm_err(host(ud), ref) <= TOL64
