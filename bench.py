@@ -1,0 +1,253 @@
+"""Benchmark of the Godunov hot path on one MI355X.
+
+Workload (one "step"): the CFL time step and one unsplit MUSCL-Hancock +
+HLLC Godunov step (minmod slopes) of a periodic 256^3 FP64 Euler box with
+log-normal density (sigma_ln = 1, k^-11/3 Gaussian random field) and
+Gaussian random velocities at rms Mach 2; dt is computed on the device each
+step (C = 0.5) and read by the step kernel, so nothing returns to the host.
+
+Prints one JSON line:
+  value     Mcell-updates/s of the whole step (cfl_dt + godunov_step)
+  roofline  the step kernel's algorithmic HBM bytes per launch / its average
+            launch time (HIP events on the launch stream) against 8 TB/s;
+            traffic = measured HBM bytes per launch from rocprofv3 counters
+            (profiles/), or null when the kernel source changed since
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+  also      the batched AMR workload (4096 ghost-zoned patches 8^3..32^3,
+            FP64 and FP32, one persistent launch per step) for the
+            plain-vs-batched comparison
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+GAMMA = 5.0 / 3.0
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mcell-updates/s per Godunov step (plain vs batched), % HBM roofline; adjoint/fwd"
+KERNEL_SRC = os.path.join(ROOT, "paper_1412_0934_amd", "csrc", "godunov_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bench_periodic(torch, gd, steps, warmup, n=256):
+    from paper_1412_0934_amd import inputs
+    log(f"bench: generating the {n}^3 periodic box")
+    u0 = inputs.turbulent_box(n, mach=2.0)
+    dx = 1.0 / n
+    ua = torch.from_numpy(u0).cuda()
+    ub = torch.empty_like(ua)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one_step(src, dst, ev=None):
+        gd.cfl_dt(src, GAMMA, dx, 0.5, periodic=True, out=dt)
+        if ev is not None:
+            ev[0].record(stream)
+        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, want_bflux=False, out=dst)
+        if ev is not None:
+            ev[1].record(stream)
+
+    log(f"bench: {warmup} warmup steps")
+    for i in range(warmup):
+        one_step(ua, ub) if i % 2 == 0 else one_step(ub, ua)
+    torch.cuda.synchronize()
+    # restart from the initial state so that every run times the same data
+    ua.copy_(torch.from_numpy(u0))
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+    torch.cuda.synchronize()
+    log(f"bench: timing {steps} steps")
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if i % 2 == 0:
+            one_step(ua, ub, events[i])
+        else:
+            one_step(ub, ua, events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in events) / steps
+    cells = n ** 3
+    return {
+        "cells": cells, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+        "step_kernel_ms": kernel_ms, "bytes_per_launch": 80.0 * cells, "u0": u0,
+    }
+
+
+def bench_batched(torch, gd, steps, warmup, dtype_name):
+    import numpy as np
+    from paper_1412_0934_amd import inputs
+    log(f"bench: batched AMR workload ({dtype_name})")
+    batch = bench_batched.cache
+    if batch is None:
+        batch = inputs.amr_batch(4096, seed=5)
+        bench_batched.cache = batch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    es = 8 if dtype == torch.float64 else 4
+    table = gd.patch_table(batch.dims, batch.ng, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, 0.0)
+    u_in = torch.from_numpy(batch.u_in).to("cuda", dtype)
+    out = torch.empty(batch.u_out_size, dtype=dtype, device="cuda")
+    flux = torch.empty(batch.flux_size, dtype=dtype, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.cfl_dt_batched(u_in, table, GAMMA, 0.5, out=dt)
+    for _ in range(warmup):
+        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    stream = torch.cuda.current_stream()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    cells = batch.interior_cells
+    # minimal traffic: the cells the stencil reads once, the interior written
+    # once, and the boundary-flux sheets written once
+    d = batch.dims.astype(np.int64)
+    read_cells = (np.prod(d, axis=1) + 4 * (d[:, 0] * d[:, 1] + d[:, 1] * d[:, 2] + d[:, 0] * d[:, 2])
+                  + 4 * (d[:, 0] + d[:, 1] + d[:, 2])).sum()
+    nbytes = es * (5 * read_cells + 5 * cells + batch.flux_size)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": "4096 ghost-zoned patches 8^3..32^3 (p=.5/.3/.15/.05), ng=2, "
+                        "sine background + Mach-3 shock, minmod+HLLC, bflux returned",
+            "dtype": dtype_name, "cells": int(cells), "ms_per_step": ms,
+            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
+            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
+bench_batched.cache = None
+
+
+def cpu_baseline(u0, budget_s=12.0, max_steps=4):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = u0.shape[1]
+    dx = 1.0 / n
+    log(f"bench: CPU oracle on {threads} threads")
+    u = u0
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        dt = oracle.cfl_dt(u, GAMMA, dx, 0.5, periodic=True)
+        u = oracle.step(u, GAMMA, dx, dt, periodic=True)[0]
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": round(steps * n ** 3 / el / 1e6, 3), "unit": "Mcell-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full steps (cfl + step) of the same {n}^3 periodic box, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(the periodic box would shard as bricks with halo exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU available", file=sys.stderr)
+        sys.exit(1)
+    from paper_1412_0934_amd import godunov as gd
+    gd.context()
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    r = bench_periodic(torch, gd, args.steps, args.warmup)
+    value = r["cells"] / (r["ms_per_step"] * 1e-3) / 1e6
+    achieved = r["bytes_per_launch"] / (r["step_kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "periodic Euler box 256^3 FP64: log-normal density (sigma_ln=1, "
+                        "k^-11/3 GRF), rms Mach 2, p = 0.6 rho/gamma, gamma=5/3; per step "
+                        "cfl_dt (C=0.5, device scalar) + godunov_step, minmod + HLLC",
+            "cells": r["cells"], "global_batch": 1, "parallelism": "none (1 GPU)",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "step_kernel<double, minmod, HLLC>", "step_kernel_ms": round(r["step_kernel_ms"], 4),
+            "algorithmic_bytes_per_launch": r["bytes_per_launch"],
+        },
+    }
+    if not args.no_batched:
+        line["also"] = {"batched": [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
+                                    bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(r["u0"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,19 +24,32 @@ initial conditions are not available; these generators stand in for them:
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass
 
+import os
+
 import numpy as np
+from scipy import fft as _fft
 
 GAMMA = 5.0 / 3.0
+_WORKERS = min(16, os.cpu_count() or 1)
 
 
-def conserved(rho, vx, vy, vz, p, gamma=GAMMA):
-    """Stack (rho, rho v, E) with E = p/(gamma-1) + rho |v|^2 / 2."""
+def conserved(rho, vx, vy, vz, p, gamma=GAMMA, out=None):
+    """Stack (rho, rho v, E) with E = p/(gamma-1) + rho |v|^2 / 2 (into `out`
+    of shape (5, ...) when given)."""
     rho, vx, vy, vz, p = (np.asarray(a, dtype=np.float64) for a in (rho, vx, vy, vz, p))
-    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
-    return np.stack([rho, rho * vx, rho * vy, rho * vz, E])
+    shape = np.broadcast_shapes(rho.shape, vx.shape, vy.shape, vz.shape, p.shape)
+    if out is None:
+        out = np.empty((5,) + shape)
+    out[0] = rho
+    out[1] = rho * vx
+    out[2] = rho * vy
+    out[3] = rho * vz
+    out[4] = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return out
 
 
 def outflow_fill(interior, ng=2):
@@ -63,21 +76,28 @@ def sod_patch(n=32, ng=2, gamma=GAMMA, noise=0.01, seed=0, axis=0):
     return outflow_fill(conserved(rho, zero, zero, zero, p, gamma), ng), 1.0 / n
 
 
-def gaussian_random_field(n, seed, spectral_index=-11.0 / 3.0):
-    """Zero-mean, unit-variance periodic field whose power spectrum is
-    P(k) ~ k^spectral_index: white noise filtered by k^(spectral_index/2)."""
-    rng = np.random.default_rng(seed)
-    white = rng.standard_normal((n, n, n))
-    fk = np.fft.rfftn(white)
+@functools.lru_cache(maxsize=4)
+def _spectral_filter(n, spectral_index):
     k1 = np.fft.fftfreq(n) * n
     kz = np.fft.rfftfreq(n) * n
     kk = np.sqrt(k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kz[None, None, :] ** 2)
     amp = np.zeros_like(kk)
     nz = kk > 0
     amp[nz] = kk[nz] ** (spectral_index / 2.0)
-    f = np.fft.irfftn(fk * amp, s=(n, n, n), axes=(0, 1, 2))
+    return amp
+
+
+def gaussian_random_field(n, seed, spectral_index=-11.0 / 3.0):
+    """Zero-mean, unit-variance periodic field whose power spectrum is
+    P(k) ~ k^spectral_index: white noise filtered by k^(spectral_index/2)."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((n, n, n))
+    fk = _fft.rfftn(white, workers=_WORKERS)
+    fk *= _spectral_filter(n, spectral_index)
+    f = _fft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2), workers=_WORKERS)
     f -= f.mean()
-    return f / f.std()
+    f /= f.std()
+    return f
 
 
 def turbulent_box(n=256, gamma=GAMMA, mach=2.0, sigma_ln=1.0, seeds=(1, 2, 3, 4)):
@@ -106,7 +126,7 @@ def _random_wavevector(rng, kmax):
             return k.astype(np.float64)
 
 
-def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0):
+def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0, out=None):
     """One ghost-zoned patch (5, nz+2ng, ny+2ng, nx+2ng): smooth sine background
     (rho and p at 1 +- 0.2, |v| <= 0.1) evaluated at cell centres from a random
     origin, cut by a planar shock of random normal through a random interior
@@ -119,10 +139,9 @@ def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0):
     normal = _random_unit(rng)
     through = origin + dx * rng.uniform(0.0, 1.0, size=3) * np.array([nx, ny, nz])
 
-    ix = origin[0] + (np.arange(-ng, nx + ng) + 0.5) * dx
-    iy = origin[1] + (np.arange(-ng, ny + ng) + 0.5) * dx
-    iz = origin[2] + (np.arange(-ng, nz + ng) + 0.5) * dx
-    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+    X = (origin[0] + (np.arange(-ng, nx + ng) + 0.5) * dx)[None, None, :]
+    Y = (origin[1] + (np.arange(-ng, ny + ng) + 0.5) * dx)[None, :, None]
+    Z = (origin[2] + (np.arange(-ng, nz + ng) + 0.5) * dx)[:, None, None]
 
     def wave(k, ph):
         return np.sin(2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
@@ -142,7 +161,7 @@ def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0):
     rho = np.where(behind, rho1 * ratio, rho1)
     p = np.where(behind, p1 * pjump, p1)
     v = [np.where(behind, v1[d] + du * normal[d], v1[d]) for d in range(3)]
-    return conserved(rho, v[0], v[1], v[2], p, gamma)
+    return conserved(rho, v[0], v[1], v[2], p, gamma, out=out)
 
 
 @dataclass
@@ -187,36 +206,40 @@ class Batch:
         return flat_flux[self.flux_off[p]:self.flux_off[p] + 10 * (nz * ny + nz * nx + ny * nx)]
 
 
-def pack_batch(states, ng, dx, order_seed=None):
-    """Pack a list of ghost-zoned (5, gz, gy, gx) states into one Batch.
+def batch_layout(dims, ng, dx, order_seed=None):
+    """An empty Batch for patches of the given interior extents (nx, ny, nz).
     With order_seed, patches are laid out in memory in a seeded random order
     (the descriptor list keeps the given order)."""
-    npatch = len(states)
-    dims = np.array([[s.shape[3] - 2 * ng, s.shape[2] - 2 * ng, s.shape[1] - 2 * ng]
-                     for s in states], dtype=np.int64)
+    dims = np.asarray(dims, dtype=np.int64).reshape(-1, 3)
+    npatch = len(dims)
     place = np.arange(npatch)
     if order_seed is not None:
         place = np.random.default_rng(order_seed).permutation(npatch)
-    in_sizes = np.array([s.size for s in states], dtype=np.int64)
+    in_sizes = 5 * np.prod(dims + 2 * ng, axis=1)
     out_sizes = 5 * np.prod(dims, axis=1)
     fl_sizes = 10 * (dims[:, 2] * dims[:, 1] + dims[:, 2] * dims[:, 0] + dims[:, 1] * dims[:, 0])
 
     def offsets(sizes):
         off = np.zeros(npatch, dtype=np.int64)
-        run = 0
-        for p in place:
-            off[p] = run
-            run += int(sizes[p])
-        return off, run
+        ordered = sizes[place]
+        off[place] = np.concatenate([[0], np.cumsum(ordered)[:-1]])
+        return off, int(sizes.sum())
 
     u_in_off, n_in = offsets(in_sizes)
     u_out_off, n_out = offsets(out_sizes)
     flux_off, n_fl = offsets(fl_sizes)
-    u_in = np.empty(n_in, dtype=np.float64)
-    for p, s in enumerate(states):
-        u_in[u_in_off[p]:u_in_off[p] + s.size] = s.ravel()
     dxs = np.full(npatch, float(dx)) if np.isscalar(dx) else np.asarray(dx, dtype=np.float64)
-    return Batch(dims, ng, dxs, u_in, u_in_off, u_out_off, flux_off, n_out, n_fl)
+    return Batch(dims, ng, dxs, np.empty(n_in, dtype=np.float64), u_in_off, u_out_off, flux_off,
+                 n_out, n_fl)
+
+
+def pack_batch(states, ng, dx, order_seed=None):
+    """Pack a list of ghost-zoned (5, gz, gy, gx) states into one Batch."""
+    dims = [[s.shape[3] - 2 * ng, s.shape[2] - 2 * ng, s.shape[1] - 2 * ng] for s in states]
+    batch = batch_layout(dims, ng, dx, order_seed)
+    for p, s in enumerate(states):
+        batch.patch_in(p)[...] = s
+    return batch
 
 
 def amr_batch(npatch=4096, seed=5, ng=2, dx=1.0 / 256, gamma=GAMMA,
@@ -226,8 +249,10 @@ def amr_batch(npatch=4096, seed=5, ng=2, dx=1.0 / 256, gamma=GAMMA,
     seeded random memory order."""
     rng = np.random.default_rng(seed)
     edge = rng.choice(np.asarray(sizes), size=npatch, p=np.asarray(probs))
-    states = [shocked_patch(rng, int(n), int(n), int(n), ng, dx, gamma, mach) for n in edge]
-    return pack_batch(states, ng, dx, order_seed=seed + 1000)
+    batch = batch_layout(np.repeat(edge[:, None], 3, axis=1), ng, dx, order_seed=seed + 1000)
+    for p, n in enumerate(edge):
+        shocked_patch(rng, int(n), int(n), int(n), ng, dx, gamma, mach, out=batch.patch_in(p))
+    return batch
 
 
 def random_patch(nx, ny, nz, ng=2, seed=0, dx=None, gamma=GAMMA, mach=3.0):
