@@ -39,6 +39,8 @@ struct gd_ctx {
     unsigned *d_u32 = nullptr;          // [0..1] work queue, [2] cfl done
     BatchCache batch;
     BatchCache cfl;                      // descriptor cache used by cfl_dt
+    double *d_adj = nullptr;             // adjoint scratch (grown on demand)
+    size_t adj_bytes = 0;
     int zlen_single = 32;
     int shape_single = gd::TILE_16x16;
     int shape_batched = gd::TILE_16x16;
@@ -292,6 +294,7 @@ int gd_destroy(gd_ctx *ctx)
         if (c->d_items) (void)hipFree(c->d_items);
         if (c->d_cfl_items) (void)hipFree(c->d_cfl_items);
     }
+    if (ctx->d_adj) (void)hipFree(ctx->d_adj);
     if (ctx->d_u64) (void)hipFree(ctx->d_u64);
     if (ctx->d_u32) (void)hipFree(ctx->d_u32);
     delete ctx;
@@ -453,11 +456,23 @@ int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int n
     P.nx = nx; P.ny = ny; P.nz = nz; P.ng = periodic ? 0 : ng; P.periodic = periodic;
     P.flux_off = lam_bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t need = gd::adjoint_scratch_bytes(P);
+    if (need > ctx->adj_bytes) {
+        // grow the scratch; work already queued may still use the old one
+        hipError_t he = hipDeviceSynchronize();
+        if (he != hipSuccess) return hip_fail(ctx, he, "adjoint scratch");
+        if (ctx->d_adj) (void)hipFree(ctx->d_adj);
+        ctx->d_adj = nullptr;
+        ctx->adj_bytes = 0;
+        if (hipMalloc((void **)&ctx->d_adj, need) != hipSuccess)
+            return fail(ctx, GD_E_NOMEM, "adjoint scratch of %zu bytes", need);
+        ctx->adj_bytes = need;
+    }
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
     int e = gd::launch_adjoint(opts->limiter, opts->riemann, P, (const double *)u_in,
                                (const double *)lam_out, (const double *)lam_bflux, (double *)lam_in,
-                               sc, dt, (hipStream_t)hip_stream);
-    if (e == (int)hipErrorNotSupported) return fail(ctx, GD_E_UNSUPPORTED, "adjoint not available");
+                               sc, dt, ctx->d_adj, s);
     if (e) return hip_fail(ctx, e, "godunov_step_adjoint launch");
     return GD_OK;
 }

@@ -63,9 +63,12 @@ int launch_cfl_single(int dtype, const PatchDesc &P, const void *u, const Scalar
                       double cfl, double *dt_out, unsigned long long *smax_bits,
                       unsigned *done, hipStream_t s);
 
+// Bytes of device scratch the adjoint of one patch needs.
+size_t adjoint_scratch_bytes(const PatchDesc &P);
+
 int launch_adjoint(int limiter, int riemann, const PatchDesc &P, const double *u_in,
                    const double *lam_out, const double *lam_bflux, double *lam_in,
-                   const Scalars &sc, double dt, hipStream_t s);
+                   const Scalars &sc, double dt, double *scratch, hipStream_t s);
 
 int max_resident_blocks(int dtype, int limiter, int riemann, int shape, int device);
 

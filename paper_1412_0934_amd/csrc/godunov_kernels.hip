@@ -31,7 +31,7 @@ int tile_ty(int shape) { return shape == TILE_8x8 ? 8 : (shape == TILE_32x8 ? 8 
 
 template <typename T>
 struct Phys {
-    T gamma, gm1, rho_floor, p_floor;
+    T gamma, gm1, inv_gm1, rho_floor, p_floor;
 };
 
 constexpr int tile_threads(int tx, int ty) { return tx * ty + ((2 * (tx + ty) + 63) / 64) * 64; }
@@ -43,6 +43,35 @@ struct TileGeom {
     static constexpr int NT = NINT + NRING;
 };
 
+// ------------------------------------------------------------ fast arithmetic
+// Reciprocal and reciprocal square root: the hardware estimate refined by
+// Newton-Raphson iterations (two for FP64, which square the relative error
+// each time; the FP32 estimate is already within an ulp). Operands are
+// normal, finite numbers here (densities, pressures and wave-speed gaps).
+
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double fast_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    double t = fma(-h * y, y, 0.5);
+    y = fma(y, t, y);
+    t = fma(-h * y, y, 0.5);
+    return fma(y, t, y);
+}
+
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // ------------------------------------------------------------ cell physics
 
 template <typename T>
@@ -50,31 +79,32 @@ __device__ __forceinline__ void prim_from_cons(const T U[5], T W[5], T &inv_rho,
                                                const Phys<T> &ph, int &hits)
 {
     T rho = U[0];
-    if (rho < ph.rho_floor) { rho = ph.rho_floor; ++hits; }
-    T inv = T(1) / rho;
+    hits += rho < ph.rho_floor;
+    rho = fmax(rho, ph.rho_floor);
+    T inv = fast_rcp(rho);
     T u = U[1] * inv, v = U[2] * inv, w = U[3] * inv;
     T kin = T(0.5) * (U[1] * u + U[2] * v + U[3] * w);
     T p = ph.gm1 * (U[4] - kin);
-    if (p < ph.p_floor) { p = ph.p_floor; ++hits; }
+    hits += p < ph.p_floor;
+    p = fmax(p, ph.p_floor);
     W[0] = rho; W[1] = u; W[2] = v; W[3] = w; W[4] = p;
     inv_rho = inv;
 }
 
+// Limited undivided slope from a = q_i - q_{i-1}, b = q_{i+1} - q_i.
+// minmod is the median of (a, b, 0); MC is sign(a) min(2|a|, 2|b|, |a+b|/2)
+// when a and b share a sign, else 0.
 template <int LIM, typename T>
 __device__ __forceinline__ T limited_slope(T a, T b)
 {
     if constexpr (LIM == LIM_NONE) {
         return T(0.5) * (a + b);
+    } else if constexpr (LIM == LIM_MINMOD) {
+        return fmax(fmin(a, b), fmin(fmax(a, b), T(0)));
     } else {
-        bool pos = a > T(0) && b > T(0);
-        bool neg = a < T(0) && b < T(0);
-        if constexpr (LIM == LIM_MINMOD) {
-            T m = fabs(a) <= fabs(b) ? a : b;
-            return (pos || neg) ? m : T(0);
-        } else {
-            T m = fmin(fmin(T(2) * fabs(a), T(2) * fabs(b)), T(0.5) * fabs(a + b));
-            return pos ? m : (neg ? -m : T(0));
-        }
+        T lo = fmin(a, b), hi = fmax(a, b);
+        T m = fmin(fmin(T(2) * fabs(a), T(2) * fabs(b)), T(0.5) * fabs(a + b));
+        return lo > T(0) ? m : (hi < T(0) ? -m : T(0));
     }
 }
 
@@ -96,13 +126,15 @@ __device__ __forceinline__ void predictor(const T W[5], T inv_rho, const T Sx[5]
 }
 
 template <typename T>
-__device__ __forceinline__ void face_state(const T Ws[5], const T S[5], T sign, T out[5],
+__device__ __forceinline__ void face_state(const T Ws[5], const T S[5], T half_sign, T out[5],
                                            const Phys<T> &ph, int &hits)
 {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) out[q] = Ws[q] + sign * T(0.5) * S[q];
-    if (out[0] < ph.rho_floor) { out[0] = ph.rho_floor; ++hits; }
-    if (out[4] < ph.p_floor) { out[4] = ph.p_floor; ++hits; }
+    for (int q = 0; q < 5; ++q) out[q] = Ws[q] + half_sign * S[q];
+    hits += out[0] < ph.rho_floor;
+    hits += out[4] < ph.p_floor;
+    out[0] = fmax(out[0], ph.rho_floor);
+    out[4] = fmax(out[4], ph.p_floor);
 }
 
 // ------------------------------------------------------------ Riemann fluxes
@@ -112,16 +144,18 @@ template <typename T>
 __device__ __forceinline__ void hllc_rotated(const T L[5], const T R[5], const Phys<T> &ph, T F[5])
 {
     const T g = ph.gamma;
-    T cL = sqrt(g * L[4] / L[0]);
-    T cR = sqrt(g * R[4] / R[0]);
+    // c = sqrt(g p / rho) = g p / sqrt(g p rho)
+    T gpL = g * L[4], gpR = g * R[4];
+    T cL = gpL * fast_rsqrt(gpL * L[0]);
+    T cR = gpR * fast_rsqrt(gpR * R[0]);
     T SL = fmin(L[1] - cL, R[1] - cR);
     T SR = fmax(L[1] + cL, R[1] + cR);
     T mL = L[0] * (SL - L[1]);
     T mR = R[0] * (SR - R[1]);
-    T Sst = (R[4] - L[4] + mL * L[1] - mR * R[1]) / (mL - mR);
+    T Sst = (R[4] - L[4] + mL * L[1] - mR * R[1]) * fast_rcp(mL - mR);
 
-    // Region logic in the order: S_L >= 0 -> F(L); S* >= 0 -> L star;
-    // S_R > 0 -> R star; else F(R). The side K whose flux is the base:
+    // Regions, in order: S_L >= 0 -> F(L); S* >= 0 -> L star; S_R > 0 ->
+    // R star; else F(R). K is the side whose flux is the base.
     bool supL = SL >= T(0);
     bool left = supL || Sst >= T(0);
     bool star = !supL && (left || SR > T(0));
@@ -131,15 +165,19 @@ __device__ __forceinline__ void hllc_rotated(const T L[5], const T R[5], const P
     T wK = left ? L[3] : R[3];
     T pK = left ? L[4] : R[4];
     T SK = left ? SL : SR;
-    T mK = left ? mL : mR;
 
-    T EK = pK / ph.gm1 + T(0.5) * rK * (uK * uK + vK * vK + wK * wK);
+    T EK = pK * ph.inv_gm1 + T(0.5) * rK * (uK * uK + vK * vK + wK * wK);
     T mass = rK * uK;
     T FK[5] = { mass, mass * uK + pK, mass * vK, mass * wK, uK * (EK + pK) };
-    T UK[5] = { rK, rK * uK, rK * vK, rK * wK, EK };
-    T a = mK / (SK - Sst);
-    T e = EK / rK + (Sst - uK) * (Sst + pK / mK);
-    T Us[5] = { a, a * Sst, a * vK, a * wK, a * e };
+    T UK[5] = { rK, mass, rK * vK, rK * wK, EK };
+    // U*_K = a (1, S*, v_K, w_K, e) with a = rho_K (S_K - u_K)/(S_K - S*) and
+    // e = E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))); the energy
+    // component a e is expanded so that only 1/(S_K - S*) is needed.
+    T dK = SK - uK;
+    T inv_d = fast_rcp(SK - Sst);
+    T a = rK * dK * inv_d;
+    T su = Sst - uK;
+    T Us[5] = { a, a * Sst, a * vK, a * wK, inv_d * (EK * dK + su * pK) + a * Sst * su };
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         T Fs = FK[q] + SK * (Us[q] - UK[q]);
@@ -150,52 +188,68 @@ __device__ __forceinline__ void hllc_rotated(const T L[5], const T R[5], const P
 template <typename T>
 __device__ __forceinline__ void euler_flux_rotated(const T W[5], const Phys<T> &ph, T F[5], T U[5])
 {
-    T E = W[4] / ph.gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+    T E = W[4] * ph.inv_gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
     T mass = W[0] * W[1];
     F[0] = mass; F[1] = mass * W[1] + W[4]; F[2] = mass * W[2]; F[3] = mass * W[3];
     F[4] = W[1] * (E + W[4]);
-    U[0] = W[0]; U[1] = W[0] * W[1]; U[2] = W[0] * W[2]; U[3] = W[0] * W[3]; U[4] = E;
+    U[0] = W[0]; U[1] = mass; U[2] = W[0] * W[2]; U[3] = W[0] * W[3]; U[4] = E;
 }
 
 template <typename T>
 __device__ __forceinline__ void hll_rotated(const T L[5], const T R[5], const Phys<T> &ph, T F[5])
 {
     const T g = ph.gamma;
-    T cL = sqrt(g * L[4] / L[0]);
-    T cR = sqrt(g * R[4] / R[0]);
+    T gpL = g * L[4], gpR = g * R[4];
+    T cL = gpL * fast_rsqrt(gpL * L[0]);
+    T cR = gpR * fast_rsqrt(gpR * R[0]);
     T SL = fmin(L[1] - cL, R[1] - cR);
     T SR = fmax(L[1] + cL, R[1] + cR);
     T FL[5], FR[5], UL[5], UR[5];
     euler_flux_rotated(L, ph, FL, UL);
     euler_flux_rotated(R, ph, FR, UR);
+    T inv = fast_rcp(SR - SL);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        T Fm = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) / (SR - SL);
+        T Fm = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) * inv;
         F[q] = SL >= T(0) ? FL[q] : (SR <= T(0) ? FR[q] : Fm);
     }
 }
 
-// Flux through a face normal to direction d (0, 1, 2; may differ per lane)
-// from unrotated primitive states. The transverse components follow the
-// cyclic order (d+1, d+2).
 template <int RS, typename T>
-__device__ __forceinline__ void face_flux(int d, const T WL[5], const T WR[5], const Phys<T> &ph,
-                                          T F[5])
+__device__ __forceinline__ void riemann(const T L[5], const T R[5], const Phys<T> &ph, T F[5])
 {
-    T L[5], R[5], G[5];
-    L[0] = WL[0]; R[0] = WR[0]; L[4] = WL[4]; R[4] = WR[4];
-    L[1] = d == 0 ? WL[1] : (d == 1 ? WL[2] : WL[3]);
-    L[2] = d == 0 ? WL[2] : (d == 1 ? WL[3] : WL[1]);
-    L[3] = d == 0 ? WL[3] : (d == 1 ? WL[1] : WL[2]);
-    R[1] = d == 0 ? WR[1] : (d == 1 ? WR[2] : WR[3]);
-    R[2] = d == 0 ? WR[2] : (d == 1 ? WR[3] : WR[1]);
-    R[3] = d == 0 ? WR[3] : (d == 1 ? WR[1] : WR[2]);
-    if constexpr (RS == RS_HLL) hll_rotated(L, R, ph, G);
-    else hllc_rotated(L, R, ph, G);
+    if constexpr (RS == RS_HLL) hll_rotated(L, R, ph, F);
+    else hllc_rotated(L, R, ph, F);
+}
+
+// Flux through a face normal to the compile-time direction D from unrotated
+// primitive states; transverse components follow the cyclic order (D+1, D+2).
+template <int RS, int D, typename T>
+__device__ __forceinline__ void face_flux(const T WL[5], const T WR[5], const Phys<T> &ph, T F[5])
+{
+    constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
+    T L[5] = { WL[0], WL[n], WL[t1], WL[t2], WL[4] };
+    T R[5] = { WR[0], WR[n], WR[t1], WR[t2], WR[4] };
+    T G[5];
+    riemann<RS>(L, R, ph, G);
+    F[0] = G[0]; F[n] = G[1]; F[t1] = G[2]; F[t2] = G[3]; F[4] = G[4];
+}
+
+// The same for a direction chosen per lane (x or y), used where one wave
+// holds faces of both orientations.
+template <int RS, typename T>
+__device__ __forceinline__ void face_flux_xy(bool isx, const T WL[5], const T WR[5],
+                                             const Phys<T> &ph, T F[5])
+{
+    // x: (u, v, w); y: (v, w, u)
+    T L[5] = { WL[0], isx ? WL[1] : WL[2], isx ? WL[2] : WL[3], isx ? WL[3] : WL[1], WL[4] };
+    T R[5] = { WR[0], isx ? WR[1] : WR[2], isx ? WR[2] : WR[3], isx ? WR[3] : WR[1], WR[4] };
+    T G[5];
+    riemann<RS>(L, R, ph, G);
     F[0] = G[0]; F[4] = G[4];
-    F[1] = d == 0 ? G[1] : (d == 1 ? G[3] : G[2]);
-    F[2] = d == 0 ? G[2] : (d == 1 ? G[1] : G[3]);
-    F[3] = d == 0 ? G[3] : (d == 1 ? G[2] : G[1]);
+    F[1] = isx ? G[1] : G[3];
+    F[2] = isx ? G[2] : G[1];
+    F[3] = isx ? G[3] : G[2];
 }
 
 // ------------------------------------------------------------ addressing
@@ -207,15 +261,20 @@ struct InputView {
     int32_t sy, sz;           // row and plane strides
     int32_t nx, ny, nz, ng, periodic;
 
-    __device__ __forceinline__ int64_t cell(int i, int j, int k) const
+    // offset of column (i, j) within a plane
+    __device__ __forceinline__ int64_t column(int i, int j) const
     {
         if (periodic) {
             i = wrap_once(wrap_once(i, nx), nx);
             j = wrap_once(wrap_once(j, ny), ny);
-            k = wrap_once(wrap_once(k, nz), nz);
-            return (int64_t)k * sz + (int64_t)j * sy + i;
+            return (int64_t)j * sy + i;
         }
-        return (int64_t)(k + ng) * sz + (int64_t)(j + ng) * sy + (i + ng);
+        return (int64_t)(j + ng) * sy + (i + ng);
+    }
+    __device__ __forceinline__ int64_t plane(int k) const
+    {
+        if (periodic) return (int64_t)wrap_once(wrap_once(k, nz), nz) * sz;
+        return (int64_t)(k + ng) * sz;
     }
 };
 
@@ -233,27 +292,42 @@ __device__ __forceinline__ InputView make_view(const PatchDesc &P)
 }
 
 template <typename T>
-__device__ __forceinline__ void load_cons(const T *__restrict__ u, const InputView &v, int i, int j,
-                                          int k, T U[5])
+__device__ __forceinline__ void load5(const T *__restrict__ p, int64_t vstride, T U[5])
 {
-    int64_t c = v.cell(i, j, k);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) U[q] = u[c + q * v.vstride];
+    for (int q = 0; q < 5; ++q) U[q] = p[q * vstride];
 }
 
 // ------------------------------------------------------------ the tile march
 
 template <typename T, int TX, int TY>
 struct TileSmem {
-    T w[5][TY + 4][TX + 4];     // primitives of the plane, two-deep halo
-    T xp[5][TY][TX + 1];        // x+ face state of cell i-1 at [i]
-    T yp[5][TY + 1][TX];        // y+ face state of cell j-1 at [j]
-    T fx[5][TY][TX + 1];        // x flux through face i-1/2 at [i]
-    T fy[5][TY + 1][TX];        // y flux through face j-1/2 at [j]
+    // primitives of planes k-1 and k (buffer k & 1), two-deep x-y halo
+    T w[2][5][TY + 4][TX + 4];
+    // face states of the plane: x face i-1/2 of row j has its left state in
+    // xl[.][j][i] and its right state in xr[.][j][i]; likewise y face j-1/2 of
+    // column i in yl/yr[.][j][i]. The flux through a face overwrites its left
+    // state (the thread that evaluates a face is the only one touching it).
+    T xl[5][TY][TX + 1];
+    T xr[5][TY][TX + 1];
+    T yl[5][TY + 1][TX];
+    T yr[5][TY + 1][TX];
 };
 
 enum { ROLE_NONE = -1, ROLE_INT = 0, ROLE_BOTTOM = 1, ROLE_TOP = 2, ROLE_LEFT = 3, ROLE_RIGHT = 4 };
 
+// One tile: interior columns [x0, x0+TX) x [y0, y0+TY) (clipped to the
+// patch), planes [z0, z1). Per plane k (after a prologue plane z0-1 that only
+// produces the z+ face states, and before an epilogue plane z1 that only
+// produces the z- face states):
+//   A  each column owner reads plane k+1 of its column, stages plane k in
+//      LDS; halo threads stage the depth-2 halo and the corner cells;
+//   B  owners: slopes, predictor, face states (x and y into LDS; the z
+//      states of interior columns stay in registers);
+//   C  all threads: the x and y faces of the plane as uniform tasks, each
+//      face once; then interior columns: the z face below the plane, which
+//      completes plane k-1;
+//   D  interior: x-y flux divergence accumulated for plane k.
 template <typename T, int LIM, int RS, int TX, int TY>
 __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
                              T *__restrict__ u_out_base, T *__restrict__ bflux_base, T dtdx, T lam,
@@ -261,13 +335,15 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                              TileSmem<T, TX, TY> &sm, int &hits)
 {
     using Geo = TileGeom<TX, TY>;
+    constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX;
+    constexpr int XVS = TY * (TX + 1), YVS = (TY + 1) * TX;    // LDS variable strides
     const int tid = threadIdx.x;
     const int ax = min(TX, P.nx - x0);
     const int ay = min(TY, P.ny - y0);
     const InputView view = make_view(P);
     const T *__restrict__ uin = u_in_base + P.in_off;
 
-    // ---- role of this thread
+    // ---- role of this thread: an interior column, a ring column, or none
     int ci = 0, cj = 0, role = ROLE_NONE;
     if (tid < Geo::NINT) {
         ci = tid % TX;
@@ -283,6 +359,7 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
     const bool owner = role != ROLE_NONE;
     const bool interior = role == ROLE_INT;
     const int gi = x0 + ci, gj = y0 + cj;     // patch coordinates of the owned column
+    const int64_t col = view.column(gi, gj);
 
     // ---- depth-2 halo and depth-1 corner cells of a plane, one per thread
     int hi = 0, hj = 0;
@@ -300,213 +377,192 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
             hj = (c & 2) ? ay : -1;
         }
     }
+    const int64_t hcol = view.column(x0 + hi, y0 + hj);
 
     // boundary-flux sheets of this patch
     const bool want_flux = bflux_base != nullptr && P.flux_off >= 0;
     T *__restrict__ bf = want_flux ? bflux_base + P.flux_off : nullptr;
     const int64_t sxs = (int64_t)P.nz * P.ny, sys = (int64_t)P.nz * P.nx, szs = (int64_t)P.ny * P.nx;
-    T *bxm = bf, *bxp = bf + 5 * sxs, *bym = bf + 10 * sxs, *byp = bym + 5 * sys;
-    T *bzm = byp + 5 * sys, *bzp = bzm + 5 * szs;
+
+    T *__restrict__ out = u_out_base + P.out_off;
+    const int64_t ostride = (int64_t)P.nx * P.ny * P.nz;
+    const int64_t ocol = (int64_t)gj * P.nx + gi;
 
     // ---- registers of the owned column
-    T Wm[5], W0[5], Wp[5], inv0 = T(1), invp = T(1);
-    T Ucur[5], Unext[5], Uprev[5];
-    T zprev[5], dxy_prev[5], Fzm[5];
+    T W0[5], Wp[5], inv0 = T(1), invp = T(1);
+    T zprev[5], acc[5], zm[5], zpn[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        Wm[q] = W0[q] = Wp[q] = T(0);
-        Ucur[q] = Unext[q] = Uprev[q] = zprev[q] = dxy_prev[q] = Fzm[q] = T(0);
+        W0[q] = Wp[q] = T(0);
+        zprev[q] = acc[q] = zm[q] = zpn[q] = T(0);
     }
 
-    // prologue: planes z0-2 (interior only), z0-1 and z0
+    // prologue: plane z0-2 (interior only, straight into its LDS buffer) and
+    // plane z0-1 (into the column registers)
     if (owner) {
-        T U[5], inv;
+        T U[5], Wt[5], inv;
         if (interior) {
-            load_cons(uin, view, gi, gj, z0 - 2, U);
-            prim_from_cons(U, Wm, inv, ph, hits);
+            load5(uin + view.plane(z0 - 2) + col, view.vstride, U);
+            prim_from_cons(U, Wt, inv, ph, hits);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.w[(z0 - 2) & 1][q][cj + 2][ci + 2] = Wt[q];
         }
-        load_cons(uin, view, gi, gj, z0 - 1, U);
-        prim_from_cons(U, W0, inv0, ph, hits);
-        load_cons(uin, view, gi, gj, z0, Unext);
-        prim_from_cons(Unext, Wp, invp, ph, hits);
+        load5(uin + view.plane(z0 - 1) + col, view.vstride, U);
+        prim_from_cons(U, Wp, invp, ph, hits);
     }
 
     const int lx = ci + 2, ly = cj + 2;
+    const T half = T(0.5);
     for (int k = z0 - 1; k <= z1; ++k) {
         const bool pre = k < z0;
         const bool post = k == z1;
+        const int cur = k & 1, prv = (k - 1) & 1;
 
-        if (!pre) {
-            // shift the column registers and read plane k+1
+        // ---- A: advance the column, stage plane k
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                Wm[q] = W0[q]; W0[q] = Wp[q];
-                Uprev[q] = Ucur[q]; Ucur[q] = Unext[q];
-            }
-            inv0 = invp;
-            if (interior || (owner && !post)) {
-                load_cons(uin, view, gi, gj, k + 1, Unext);
-                prim_from_cons(Unext, Wp, invp, ph, hits);
-            }
+        for (int q = 0; q < 5; ++q) W0[q] = Wp[q];
+        inv0 = invp;
+        if (interior || (owner && !post)) {
+            T U[5];
+            load5(uin + view.plane(k + 1) + col, view.vstride, U);
+            prim_from_cons(U, Wp, invp, ph, hits);
         }
-
-        // stage plane k in LDS
         if (owner) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) sm.w[q][ly][lx] = W0[q];
+            for (int q = 0; q < 5; ++q) sm.w[cur][q][ly][lx] = W0[q];
         }
         if (!pre && !post && halo) {
             T U[5], Wh[5], invh;
-            load_cons(uin, view, x0 + hi, y0 + hj, k, U);
+            load5(uin + view.plane(k) + hcol, view.vstride, U);
             prim_from_cons(U, Wh, invh, ph, hits);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) sm.w[q][hj + 2][hi + 2] = Wh[q];
+            for (int q = 0; q < 5; ++q) sm.w[cur][q][hj + 2][hi + 2] = Wh[q];
         }
         __syncthreads();
 
-        if (pre || post) {
-            // only the z face state of the interior is needed
-            if (interior) {
-                T Sx[5], Sy[5], Sz[5], Ws[5], st[5];
-#pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    T c = W0[q];
-                    Sx[q] = limited_slope<LIM>(c - sm.w[q][ly][lx - 1], sm.w[q][ly][lx + 1] - c);
-                    Sy[q] = limited_slope<LIM>(c - sm.w[q][ly - 1][lx], sm.w[q][ly + 1][lx] - c);
-                    Sz[q] = limited_slope<LIM>(c - Wm[q], Wp[q] - c);
-                }
-                predictor(W0, inv0, Sx, Sy, Sz, lam, ph.gamma, Ws);
-                if (pre) {
-                    face_state(Ws, Sz, T(1), zprev, ph, hits);
-                } else {
-                    face_state(Ws, Sz, T(-1), st, ph, hits);
-                    T Fz[5];
-                    face_flux<RS>(2, zprev, st, ph, Fz);
-                    if (want_flux && k == P.nz) {
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) bzp[q * szs + (int64_t)gj * P.nx + gi] = Fz[q];
-                    }
-                    if (k > z0) {
-                        T *out = u_out_base + P.out_off;
-                        int64_t o = ((int64_t)(k - 1) * P.ny + gj) * P.nx + gi;
-                        int64_t ostride = (int64_t)P.nx * P.ny * P.nz;
-#pragma unroll
-                        for (int q = 0; q < 5; ++q)
-                            out[o + q * ostride] = Uprev[q] - dtdx * (dxy_prev[q] + (Fz[q] - Fzm[q]));
-                    }
-                }
-            }
-            __syncthreads();
-            continue;
-        }
-
-        // ---- full plane: slopes, predictor, face states
-        T xm[5], ym[5], zm[5], zp[5];
-        if (owner) {
+        // ---- B: slopes, predictor, face states
+        const bool work = pre || post ? interior : owner;
+        if (work) {
             T Sx[5], Sy[5], Sz[5], Ws[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
                 T c = W0[q];
-                Sx[q] = limited_slope<LIM>(c - sm.w[q][ly][lx - 1], sm.w[q][ly][lx + 1] - c);
-                Sy[q] = limited_slope<LIM>(c - sm.w[q][ly - 1][lx], sm.w[q][ly + 1][lx] - c);
-                Sz[q] = limited_slope<LIM>(c - Wm[q], Wp[q] - c);
+                Sx[q] = limited_slope<LIM>(c - sm.w[cur][q][ly][lx - 1], sm.w[cur][q][ly][lx + 1] - c);
+                Sy[q] = limited_slope<LIM>(c - sm.w[cur][q][ly - 1][lx], sm.w[cur][q][ly + 1][lx] - c);
+                Sz[q] = limited_slope<LIM>(c - sm.w[prv][q][ly][lx], Wp[q] - c);
             }
             predictor(W0, inv0, Sx, Sy, Sz, lam, ph.gamma, Ws);
-            T st[5];
-            if (interior || role == ROLE_LEFT) {
-                face_state(Ws, Sx, T(1), st, ph, hits);
+            if (pre) {
+                face_state(Ws, Sz, half, zprev, ph, hits);
+            } else if (post) {
+                face_state(Ws, Sz, -half, zm, ph, hits);
+            } else {
+                T st[5];
+                if (interior || role == ROLE_LEFT) {
+                    face_state(Ws, Sx, half, st, ph, hits);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) sm.xp[q][cj][ci + 1] = st[q];
-            }
-            if (interior || role == ROLE_BOTTOM) {
-                face_state(Ws, Sy, T(1), st, ph, hits);
+                    for (int q = 0; q < 5; ++q) sm.xl[q][cj][ci + 1] = st[q];
+                }
+                if (interior || role == ROLE_RIGHT) {
+                    face_state(Ws, Sx, -half, st, ph, hits);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) sm.yp[q][cj + 1][ci] = st[q];
-            }
-            if (interior || role == ROLE_RIGHT) face_state(Ws, Sx, T(-1), xm, ph, hits);
-            if (interior || role == ROLE_TOP) face_state(Ws, Sy, T(-1), ym, ph, hits);
-            if (interior) {
-                face_state(Ws, Sz, T(-1), zm, ph, hits);
-                face_state(Ws, Sz, T(1), zp, ph, hits);
+                    for (int q = 0; q < 5; ++q) sm.xr[q][cj][ci] = st[q];
+                }
+                if (interior || role == ROLE_BOTTOM) {
+                    face_state(Ws, Sy, half, st, ph, hits);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) sm.yl[q][cj + 1][ci] = st[q];
+                }
+                if (interior || role == ROLE_TOP) {
+                    face_state(Ws, Sy, -half, st, ph, hits);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) sm.yr[q][cj][ci] = st[q];
+                }
+                if (interior) {
+                    face_state(Ws, Sz, -half, zm, ph, hits);
+                    face_state(Ws, Sz, half, zpn, ph, hits);
+                }
             }
         }
-        __syncthreads();
+        if (!post) __syncthreads();
+        if (pre) continue;
 
-        // ---- fluxes, each face once
-        T Fz[5];
+        // ---- C1: x and y faces as tasks over all threads. Task t < NXF is
+        // x face (i, j) = (t % (TX+1), t / (TX+1)); the rest are y faces
+        // (i, j) = (u % TX, u / TX) with u = t - NXF. States are read and
+        // fluxes written through per-lane LDS addresses in rotated order
+        // (normal velocity first), so one code path serves both directions.
+        if (!post) {
+            for (int t = tid; t < NXF + NYF; t += Geo::NT) {
+                const bool isx = t < NXF;
+                const int u = isx ? t : t - NXF;
+                const int i = isx ? u % (TX + 1) : u % TX;
+                const int j = isx ? u / (TX + 1) : u / TX;
+                const bool active = isx ? (i <= ax && j < ay) : (i < ax && j <= ay);
+                if (!active) continue;
+                T *lb = isx ? &sm.xl[0][j][i] : &sm.yl[0][j][i];
+                const T *rb = isx ? &sm.xr[0][j][i] : &sm.yr[0][j][i];
+                const int vs = isx ? XVS : YVS;
+                // rotated component offsets: x (u, v, w), y (v, w, u)
+                const int on = (isx ? 1 : 2) * vs, o1 = (isx ? 2 : 3) * vs, o2 = (isx ? 3 : 1) * vs;
+                T L[5] = { lb[0], lb[on], lb[o1], lb[o2], lb[4 * vs] };
+                T R[5] = { rb[0], rb[on], rb[o1], rb[o2], rb[4 * vs] };
+                T G[5];
+                riemann<RS>(L, R, ph, G);
+                lb[0] = G[0]; lb[on] = G[1]; lb[o1] = G[2]; lb[o2] = G[3]; lb[4 * vs] = G[4];
+                if (want_flux) {
+                    const int fi = x0 + i, fj = y0 + j;
+                    T F[5];
+                    F[0] = G[0]; F[4] = G[4];
+                    F[1] = isx ? G[1] : G[3];
+                    F[2] = isx ? G[2] : G[1];
+                    F[3] = isx ? G[3] : G[2];
+                    if (isx && (fi == 0 || fi == P.nx)) {
+                        T *sheet = bf + (fi == 0 ? 0 : 5 * sxs);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) sheet[q * sxs + (int64_t)k * P.ny + fj] = F[q];
+                    }
+                    if (!isx && (fj == 0 || fj == P.ny)) {
+                        T *sheet = bf + 10 * sxs + (fj == 0 ? 0 : 5 * sys);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) sheet[q * sys + (int64_t)k * P.nx + fi] = F[q];
+                    }
+                }
+            }
+        }
+
+        // ---- C2: the z face below the plane; completes plane k-1
         if (interior) {
-            T L[5], F[5];
+            T F[5];
+            face_flux<RS, 2>(zprev, zm, ph, F);
+            if (want_flux && (k == 0 || k == P.nz)) {
+                T *sheet = bf + 10 * sxs + 10 * sys + (k == 0 ? 0 : 5 * szs);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) L[q] = sm.xp[q][cj][ci];
-            face_flux<RS>(0, L, xm, ph, F);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) sm.fx[q][cj][ci] = F[q];
-            if (want_flux && gi == 0) {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) bxm[q * sxs + (int64_t)k * P.ny + gj] = F[q];
+                for (int q = 0; q < 5; ++q) sheet[q * szs + (int64_t)gj * P.nx + gi] = F[q];
             }
+            if (k > z0) {
+                // U' = U - dt/dx (acc + F_z(k-1/2)), acc = div_xy(k-1) - F_z(k-3/2)
+                T U[5];
+                load5(uin + view.plane(k - 1) + col, view.vstride, U);
+                T *o = out + (int64_t)(k - 1) * P.nx * P.ny + ocol;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) L[q] = sm.yp[q][cj][ci];
-            face_flux<RS>(1, L, ym, ph, F);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) sm.fy[q][cj][ci] = F[q];
-            if (want_flux && gj == 0) {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) bym[q * sys + (int64_t)k * P.nx + gi] = F[q];
+                for (int q = 0; q < 5; ++q) o[q * ostride] = U[q] - dtdx * (acc[q] + F[q]);
             }
-            face_flux<RS>(2, zprev, zm, ph, Fz);
-            if (want_flux && k == 0) {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) bzm[q * szs + (int64_t)gj * P.nx + gi] = Fz[q];
-            }
-        } else if (role == ROLE_RIGHT || role == ROLE_TOP) {
-            // the last x face (right ring) or y face (top ring) of the tile
-            const bool isx = role == ROLE_RIGHT;
-            T L[5], R[5], F[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                L[q] = isx ? sm.xp[q][cj][ax] : sm.yp[q][ay][ci];
-                R[q] = isx ? xm[q] : ym[q];
-            }
-            face_flux<RS>(isx ? 0 : 1, L, R, ph, F);
-            if (isx) {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) sm.fx[q][cj][ax] = F[q];
-                if (want_flux && gi == P.nx) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) bxp[q * sxs + (int64_t)k * P.ny + gj] = F[q];
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) sm.fy[q][ay][ci] = F[q];
-                if (want_flux && gj == P.ny) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) byp[q * sys + (int64_t)k * P.nx + gi] = F[q];
-                }
+                acc[q] = -F[q];
+                zprev[q] = zpn[q];
             }
         }
+        if (post) break;
         __syncthreads();
 
-        // ---- x-y flux divergence; finish the plane below
+        // ---- D: x-y flux divergence of the plane
         if (interior) {
-            T dxy[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q)
-                dxy[q] = (sm.fx[q][cj][ci + 1] - sm.fx[q][cj][ci]) + (sm.fy[q][cj + 1][ci] - sm.fy[q][cj][ci]);
-            if (k > z0) {
-                T *out = u_out_base + P.out_off;
-                int64_t o = ((int64_t)(k - 1) * P.ny + gj) * P.nx + gi;
-                int64_t ostride = (int64_t)P.nx * P.ny * P.nz;
-#pragma unroll
-                for (int q = 0; q < 5; ++q)
-                    out[o + q * ostride] = Uprev[q] - dtdx * (dxy_prev[q] + (Fz[q] - Fzm[q]));
-            }
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                dxy_prev[q] = dxy[q];
-                Fzm[q] = Fz[q];
-                zprev[q] = zp[q];
-            }
+                acc[q] = ((sm.xl[q][cj][ci + 1] - sm.xl[q][cj][ci]) +
+                          (sm.yl[q][cj + 1][ci] - sm.yl[q][cj][ci])) + acc[q];
         }
     }
 }
@@ -517,6 +573,7 @@ __device__ __forceinline__ Phys<T> make_phys(const Scalars &sc)
     Phys<T> ph;
     ph.gamma = T(sc.gamma);
     ph.gm1 = T(sc.gamma - 1.0);
+    ph.inv_gm1 = T(1.0 / (sc.gamma - 1.0));
     ph.rho_floor = T(sc.rho_floor);
     ph.p_floor = T(sc.p_floor);
     return ph;
@@ -527,21 +584,26 @@ __device__ __forceinline__ void flush_hits(int hits, unsigned long long *counter
     if (hits) atomicAdd(counter, (unsigned long long)hits);
 }
 
-// One patch: blockIdx.x enumerates (segment, tile) with the z segment
-// fastest, so consecutive workgroups share halo planes in L2.
+// One patch. Workgroups are dispatched round-robin over the 8 XCDs (each
+// with its own L2); the block index is remapped so that each XCD works
+// through a contiguous range of items, ordered z-segment-major then tile
+// row-major, so that tiles sharing halo columns run on the same L2.
 template <typename T, int LIM, int RS, int TX, int TY>
 __global__ __launch_bounds__(tile_threads(TX, TY)) void step_kernel(
     PatchDesc P, const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ bflux,
-    const double *__restrict__ dt_dev, Scalars sc, unsigned long long *hits_ctr, int ntx, int nseg,
+    const double *__restrict__ dt_dev, Scalars sc, unsigned long long *hits_ctr, int ntx, int nty,
     int zlen)
 {
     __shared__ TileSmem<T, TX, TY> sm;
     const Phys<T> ph = make_phys<T>(sc);
     const double dt = dt_dev ? *dt_dev : P.dt;
     const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
-    const int item = blockIdx.x;
-    const int seg = item % nseg;
-    const int tile = item / nseg;
+    const int nblocks = gridDim.x, b = blockIdx.x;
+    const int per_xcd = nblocks / 8;
+    const int item = b < 8 * per_xcd ? (b % 8) * per_xcd + b / 8 : b;
+    const int ntiles = ntx * nty;
+    const int seg = item / ntiles;
+    const int tile = item % ntiles;
     const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
     const int z0 = seg * zlen, z1 = min(z0 + zlen, P.nz);
     int hits = 0;
@@ -651,7 +713,7 @@ __global__ __launch_bounds__(256) void cfl_kernel(const PatchDesc *__restrict__ 
         for (int e = threadIdx.x; e < n; e += blockDim.x) {
             int i = e % P.nx, j = c.j0 + e / P.nx;
             T U[5];
-            load_cons(base, view, i, j, c.k, U);
+            load5(base + view.plane(c.k) + view.column(i, j), view.vstride, U);
             vmax = fmax(vmax, cell_signal(U, ph, hits) * inv_dx);
         }
     }
@@ -678,7 +740,7 @@ __global__ __launch_bounds__(256) void cfl_single_kernel(PatchDesc P, const T *_
         int64_t r = e / P.nx;
         int j = (int)(r % P.ny), k = (int)(r / P.ny);
         T U[5];
-        load_cons(base, view, i, j, k, U);
+        load5(base + view.plane(k) + view.column(i, j), view.vstride, U);
         vmax = fmax(vmax, cell_signal(U, ph, hits) * inv_dx);
     }
     cfl_finish(vmax, cfl, dt_out, smax_bits, done);
@@ -697,7 +759,7 @@ static int launch_step_t(const PatchDesc &P, const void *u_in, void *u_out, void
     if (nblocks <= 0 || nblocks > 0x7fffffff) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL((step_kernel<T, LIM, RS, TX, TY>), dim3((unsigned)nblocks),
                        dim3(TileGeom<TX, TY>::NT), 0, s, P, (const T *)u_in, (T *)u_out, (T *)bflux,
-                       dt_dev, sc, hits, ntx, nseg, zlen);
+                       dt_dev, sc, hits, ntx, nty, zlen);
     return (int)hipGetLastError();
 }
 
