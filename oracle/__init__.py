@@ -20,8 +20,11 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = os.path.join(_HERE, "liboracle.so")
-_LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
+# The pin tests can be pointed at a deliberately broken copy of the oracle
+# (tests/test_oracle_mutations.py) through ORACLE_LIB_DIR.
+_LIB_DIR = os.environ.get("ORACLE_LIB_DIR", _HERE)
+_LIB = os.path.join(_LIB_DIR, "liboracle.so")
+_LIB_CS = os.path.join(_LIB_DIR, "liboracle_cs.so")
 
 LIMITERS = {"minmod": 0, "mc": 1, "none": 2, "unlimited": 2}
 RIEMANN = {"hllc": 0, "hll": 1}
@@ -29,13 +32,14 @@ RHO_FLOOR = 1e-10
 P_FLOOR = 1e-10
 
 
-def build(verbose: bool = False) -> None:
+def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE) -> None:
     """Compile both oracle libraries with gcc (plain C11 + OpenMP)."""
     common = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v2"]
     cmds = [
-        common + ["-o", _LIB, os.path.join(_HERE, "godunov_oracle_adjoint.c"), "-lm"],
-        common + ["-DORACLE_COMPLEX_STEP", "-o", _LIB_CS,
-                  os.path.join(_HERE, "godunov_oracle.c"), "-lm"],
+        common + ["-o", os.path.join(out_dir, "liboracle.so"),
+                  os.path.join(src_dir, "godunov_oracle_adjoint.c"), "-lm"],
+        common + ["-DORACLE_COMPLEX_STEP", "-o", os.path.join(out_dir, "liboracle_cs.so"),
+                  os.path.join(src_dir, "godunov_oracle.c"), "-lm"],
     ]
     for cmd in cmds:
         if verbose:
