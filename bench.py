@@ -84,6 +84,10 @@ def bench_periodic(torch, gd, steps, warmup, n=256):
         if ev is not None:
             ev[1].record(stream)
 
+    log("bench: autotuning the step kernel")
+    dt_host = 0.5 * dx / 8.0
+    gd.autotune_step(ua, GAMMA, dx, dt_host, periodic=True, out=ub)
+    log(f"bench: config {gd.get_config(torch.float64)}")
     log(f"bench: {warmup} warmup steps")
     for i in range(warmup):
         one_step(ua, ub) if i % 2 == 0 else one_step(ub, ua)
@@ -127,6 +131,8 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
     flux = torch.empty(batch.flux_size, dtype=dtype, device="cuda")
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
     gd.cfl_dt_batched(u_in, table, GAMMA, 0.5, out=dt)
+    gd.autotune_batched(u_in, table, GAMMA, out=out, bflux=flux)
+    log(f"bench: batched config {gd.get_config(dtype)}")
     for _ in range(warmup):
         gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt)
     torch.cuda.synchronize()
@@ -149,6 +155,7 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"workload": "4096 ghost-zoned patches 8^3..32^3 (p=.5/.3/.15/.05), ng=2, "
                         "sine background + Mach-3 shock, minmod+HLLC, bflux returned",
+            "config": gd.get_config(dtype),
             "dtype": dtype_name, "cells": int(cells), "ms_per_step": ms,
             "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
             "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
@@ -238,6 +245,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel": "step_kernel<double, minmod, HLLC>", "step_kernel_ms": round(r["step_kernel_ms"], 4),
+            "tile_config": gd.get_config(torch.float64),
             "algorithmic_bytes_per_launch": r["bytes_per_launch"],
         },
     }

@@ -41,9 +41,11 @@ struct gd_ctx {
     BatchCache cfl;                      // descriptor cache used by cfl_dt
     double *d_adj = nullptr;             // adjoint scratch (grown on demand)
     size_t adj_bytes = 0;
-    int zlen_single = 32;
-    int shape_single = gd::TILE_16x16;
-    int shape_batched = gd::TILE_16x16;
+    // tuned configuration per dtype (index 0: FP64, 1: FP32)
+    int zlen_single[2] = { 32, 32 };
+    int shape_single[2] = { gd::TILE_16x16, gd::TILE_16x16 };
+    int shape_batched[2] = { gd::TILE_16x16, gd::TILE_16x16 };
+    int zpolicy_batched[2] = { 1, 1 };
 };
 
 namespace {
@@ -169,13 +171,21 @@ gd::PatchDesc to_desc(const gd_patch &p, bool periodic)
 // z-range length of batched items by patch size: long enough to amortise the
 // two extra planes a march reads, short enough to spread a patch over
 // several workgroups.
-int batched_zlen(int nz) { return nz <= 16 ? nz : (nz <= 32 ? (nz + 1) / 2 : 16); }
+// Policies: 0 = ranges of 8 planes, 1 = ranges of 16 planes (a patch of up
+// to 32 planes is split in two), 2 = the whole patch in one range.
+int batched_zlen(int nz, int policy)
+{
+    if (policy == 0) return std::min(nz, 8);
+    if (policy == 2) return nz;
+    return nz <= 16 ? nz : (nz <= 32 ? (nz + 1) / 2 : 16);
+}
 
-int build_step_tables(gd_ctx *ctx, int dtype, int shape, int npatch, const gd_patch *patches,
-                      hipStream_t s)
+int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch,
+                      const gd_patch *patches, hipStream_t s)
 {
     BatchCache &c = ctx->batch;
-    if (c.dtype == dtype && c.shape == shape && same_patches(c, npatch, patches)) return GD_OK;
+    const int tag = dtype * 16 + zpolicy;
+    if (c.dtype == tag && c.shape == shape && same_patches(c, npatch, patches)) return GD_OK;
     const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
     std::vector<gd::PatchDesc> desc(npatch);
     std::vector<gd::WorkItem> items;
@@ -187,7 +197,7 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int npatch, const gd_pa
     std::stable_sort(order.begin(), order.end());
     for (auto &o : order) {
         const gd_patch &p = patches[o.second];
-        const int zl = batched_zlen(p.nz);
+        const int zl = batched_zlen(p.nz, zpolicy);
         for (int z0 = 0; z0 < p.nz; z0 += zl)
             for (int y0 = 0; y0 < p.ny; y0 += TY)
                 for (int x0 = 0; x0 < p.nx; x0 += TX) {
@@ -211,7 +221,7 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int npatch, const gd_pa
     if (e != hipSuccess) return hip_fail(ctx, e, "upload of batch tables");
     c.host.assign(patches, patches + npatch);
     c.nitems = (int)items.size();
-    c.dtype = dtype;
+    c.dtype = tag;
     c.shape = shape;
     return GD_OK;
 }
@@ -356,9 +366,9 @@ int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int n
     P.in_off = 0; P.out_off = 0; P.flux_off = bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
-    int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann, ctx->shape_single, P, u_in,
-                            u_out, bflux, dt_dev, sc, ctx->d_u64, ctx->zlen_single,
-                            (hipStream_t)hip_stream);
+    int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann,
+                            ctx->shape_single[opts->dtype], P, u_in, u_out, bflux, dt_dev, sc,
+                            ctx->d_u64, ctx->zlen_single[opts->dtype], (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "godunov_step launch");
     return GD_OK;
 }
@@ -390,7 +400,9 @@ int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
-    if ((r = build_step_tables(ctx, opts->dtype, ctx->shape_batched, npatch, patches, s))) return r;
+    if ((r = build_step_tables(ctx, opts->dtype, ctx->shape_batched[opts->dtype],
+                               ctx->zpolicy_batched[opts->dtype], npatch, patches, s)))
+        return r;
     const BatchCache &c = ctx->batch;
     int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, c.shape, ctx->device);
     int grid = std::min(c.nitems, per_cu * ctx->num_cus);
@@ -474,6 +486,140 @@ int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int n
                                (const double *)lam_out, (const double *)lam_bflux, (double *)lam_in,
                                sc, dt, ctx->d_adj, s);
     if (e) return hip_fail(ctx, e, "godunov_step_adjoint launch");
+    return GD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ autotuning
+
+namespace {
+
+// Mean time in ms of `reps` calls of fn() on stream s after one warm-up.
+template <typename Fn>
+int time_calls(gd_ctx *ctx, hipStream_t s, int reps, Fn fn, float *ms)
+{
+    int r = fn();
+    if (r) return r;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return fail(ctx, GD_E_HIP, "hipEventCreate");
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(ctx, GD_E_HIP, "hipEventCreate");
+    }
+    hipError_t e = hipEventRecord(a, s);
+    for (int i = 0; i < reps && e == hipSuccess && r == GD_OK; ++i) r = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (r) return r;
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune timing");
+    *ms = t / reps;
+    return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                     const void *u_in, void *u_out, double gamma, double dx, double dt,
+                     void *hip_stream, int *choice)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    const int dt_i = opts->dtype;
+    const int shapes[3] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8 };
+    const int zlens[3] = { 16, 32, 64 };
+    const int keep_shape = ctx->shape_single[dt_i], keep_zlen = ctx->zlen_single[dt_i];
+    float best = 1e30f;
+    int best_i = -1;
+    for (int si = 0; si < 3; ++si)
+        for (int zi = 0; zi < 3; ++zi) {
+            ctx->shape_single[dt_i] = shapes[si];
+            ctx->zlen_single[dt_i] = zlens[zi];
+            float ms = 0.f;
+            r = time_calls(ctx, (hipStream_t)hip_stream, 3, [&] {
+                return godunov_step(ctx, opts, nx, ny, nz, ng, u_in, u_out, nullptr, gamma, dx,
+                                    dt, nullptr, hip_stream);
+            }, &ms);
+            if (r) {
+                ctx->shape_single[dt_i] = keep_shape;
+                ctx->zlen_single[dt_i] = keep_zlen;
+                return r;
+            }
+            if (ms < best) { best = ms; best_i = si * 3 + zi; }
+        }
+    ctx->shape_single[dt_i] = shapes[best_i / 3];
+    ctx->zlen_single[dt_i] = zlens[best_i % 3];
+    if (choice) *choice = best_i;
+    return GD_OK;
+}
+
+int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+                        const void *u_in_base, void *u_out_base, void *bflux_base, double gamma,
+                        void *hip_stream, int *choice)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    const int dt_i = opts->dtype;
+    const int shapes[3] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8 };
+    const int keep_shape = ctx->shape_batched[dt_i], keep_pol = ctx->zpolicy_batched[dt_i];
+    float best = 1e30f;
+    int best_i = -1;
+    for (int si = 0; si < 3; ++si)
+        for (int zp = 0; zp < 3; ++zp) {
+            ctx->shape_batched[dt_i] = shapes[si];
+            ctx->zpolicy_batched[dt_i] = zp;
+            float ms = 0.f;
+            r = time_calls(ctx, (hipStream_t)hip_stream, 3, [&] {
+                return godunov_step_batched(ctx, opts, npatch, patches, u_in_base, u_out_base,
+                                            bflux_base, nullptr, gamma, hip_stream);
+            }, &ms);
+            if (r) {
+                ctx->shape_batched[dt_i] = keep_shape;
+                ctx->zpolicy_batched[dt_i] = keep_pol;
+                return r;
+            }
+            if (ms < best) { best = ms; best_i = si * 3 + zp; }
+        }
+    ctx->shape_batched[dt_i] = shapes[best_i / 3];
+    ctx->zpolicy_batched[dt_i] = best_i % 3;
+    if (choice) *choice = best_i;
+    return GD_OK;
+}
+
+int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single, int *shape_batched,
+                  int *zpolicy_batched)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if (dtype != GD_F64 && dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", dtype);
+    if (shape_single) *shape_single = ctx->shape_single[dtype];
+    if (zlen_single) *zlen_single = ctx->zlen_single[dtype];
+    if (shape_batched) *shape_batched = ctx->shape_batched[dtype];
+    if (zpolicy_batched) *zpolicy_batched = ctx->zpolicy_batched[dtype];
+    return GD_OK;
+}
+
+int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int shape_batched,
+                  int zpolicy_batched)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if (dtype != GD_F64 && dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", dtype);
+    if (shape_single < 0 || shape_single >= gd::NUM_TILE_SHAPES || shape_batched < 0 ||
+        shape_batched >= gd::NUM_TILE_SHAPES)
+        return fail(ctx, GD_E_ARG, "bad tile shape");
+    if (zlen_single < 1 || zlen_single > 4096) return fail(ctx, GD_E_ARG, "bad z-range length");
+    if (zpolicy_batched < 0 || zpolicy_batched > 2) return fail(ctx, GD_E_ARG, "bad z-range policy");
+    ctx->shape_single[dtype] = shape_single;
+    ctx->zlen_single[dtype] = zlen_single;
+    ctx->shape_batched[dtype] = shape_batched;
+    ctx->zpolicy_batched[dtype] = zpolicy_batched;
     return GD_OK;
 }
 

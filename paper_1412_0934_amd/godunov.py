@@ -58,7 +58,8 @@ PATCH_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("ng", "<i4
 assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
 
 EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
-           "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt")
+           "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt",
+           "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config")
 
 _lib = None
 _lock = threading.Lock()
@@ -87,6 +88,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.godunov_step_adjoint.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, vp, vp,
                                              dbl, dbl, dbl, vp]
         lib.cfl_dt.argtypes = [vp, P(gd_opts), i32, vp, vp, dbl, dbl, vp, vp]
+        ip = P(ctypes.c_int)
+        lib.gd_autotune_step.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, dbl, dbl, dbl,
+                                         vp, ip]
+        lib.gd_autotune_batched.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, dbl, vp, ip]
+        lib.gd_get_config.argtypes = [vp, i32, ip, ip, ip, ip]
+        lib.gd_set_config.argtypes = [vp, i32, i32, i32, i32, i32]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -284,6 +291,55 @@ def step_adjoint(u, lam_out, gamma, dx, dt, *, lam_bflux=None, ng=2, periodic=Fa
                                            _ptr(lam_out), _ptr(lam_bflux), _ptr(out),
                                            float(gamma), float(dx), float(dt), _stream(stream)))
     return out
+
+
+TILE_SHAPES = ("16x16", "8x8", "32x8")
+
+
+def autotune_step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", riemann="hllc",
+                  out=None, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None) -> int:
+    """Time the tile/z-range candidates of godunov_step on this problem and
+    keep the fastest in the context. Returns the candidate index."""
+    _check_tensor(u, "u")
+    nx, ny, nz = interior_shape(u, ng, periodic)
+    if out is None:
+        out = torch.empty((5, nz, ny, nx), dtype=u.dtype, device=u.device)
+    ctx = context(u.device.index)
+    o = _opts(u.dtype, periodic, limiter, riemann, rho_floor, p_floor)
+    choice = ctypes.c_int(-1)
+    ctx.check(ctx.lib.gd_autotune_step(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u),
+                                       _ptr(out), float(gamma), float(dx), float(dt),
+                                       _stream(stream), ctypes.byref(choice)))
+    return choice.value
+
+
+def autotune_batched(u_in, table, gamma, *, out, bflux=None, limiter="minmod", riemann="hllc",
+                     rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None) -> int:
+    _check_tensor(u_in, "u_in")
+    table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    ctx = context(u_in.device.index)
+    o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
+    choice = ctypes.c_int(-1)
+    ctx.check(ctx.lib.gd_autotune_batched(ctx.handle, ctypes.byref(o), len(table),
+                                          table.ctypes.data, _ptr(u_in), _ptr(out), _ptr(bflux),
+                                          float(gamma), _stream(stream), ctypes.byref(choice)))
+    return choice.value
+
+
+def get_config(dtype=torch.float64) -> dict:
+    ctx = context()
+    v = [ctypes.c_int() for _ in range(4)]
+    ctx.check(ctx.lib.gd_get_config(ctx.handle, DTYPES[dtype], *[ctypes.byref(x) for x in v]))
+    return {"shape_single": TILE_SHAPES[v[0].value], "zlen_single": v[1].value,
+            "shape_batched": TILE_SHAPES[v[2].value], "zpolicy_batched": v[3].value}
+
+
+def set_config(dtype=torch.float64, *, shape_single="16x16", zlen_single=32,
+               shape_batched="16x16", zpolicy_batched=1) -> None:
+    ctx = context()
+    ctx.check(ctx.lib.gd_set_config(ctx.handle, DTYPES[dtype], TILE_SHAPES.index(shape_single),
+                                    int(zlen_single), TILE_SHAPES.index(shape_batched),
+                                    int(zpolicy_batched)))
 
 
 class GodunovRollout(torch.autograd.Function):
