@@ -1,13 +1,14 @@
 """Benchmark of the Godunov hot path on one MI355X.
 
-Workload (one "step"): the CFL time step and one unsplit MUSCL-Hancock +
-HLLC Godunov step (minmod slopes) of a periodic 256^3 FP64 Euler box with
-log-normal density (sigma_ln = 1, k^-11/3 Gaussian random field) and
-Gaussian random velocities at rms Mach 2; dt is computed on the device each
-step (C = 0.5) and read by the step kernel, so nothing returns to the host.
+Workload (one "step"): one unsplit MUSCL-Hancock + HLLC Godunov step
+(minmod slopes) of a periodic 256^3 FP64 Euler box with log-normal density
+(sigma_ln = 1, k^-11/3 Gaussian random field) and Gaussian random velocities
+at rms Mach 2, including the CFL reduction (C = 0.5): each step launch reads
+dt from a device scalar and reduces the next dt from the state it writes
+(godunov_step_cfl), so a step is one launch and nothing returns to the host.
 
 Prints one JSON line:
-  value     Mcell-updates/s of the whole step (cfl_dt + godunov_step)
+  value     Mcell-updates/s of the whole step (step + CFL reduction)
   roofline  the step kernel's algorithmic HBM bytes per launch / its average
             launch time (HIP events on the launch stream) against 8 TB/s;
             traffic = measured HBM bytes per launch from rocprofv3 counters
@@ -66,7 +67,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_periodic(torch, gd, steps, warmup, n=256):
+def bench_periodic(torch, gd, steps, warmup, n=256, tile=None, zlen=None):
     from paper_1412_0934_amd import inputs
     log(f"bench: generating the {n}^3 periodic box")
     u0 = inputs.turbulent_box(n, mach=2.0)
@@ -76,24 +77,34 @@ def bench_periodic(torch, gd, steps, warmup, n=256):
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    # One launch per step: the step kernel reads dt from the device scalar and,
+    # from the state it writes, reduces the CFL step for the next step into
+    # the same scalar; the first dt comes from one cfl_dt call.
     def one_step(src, dst, ev=None):
-        gd.cfl_dt(src, GAMMA, dx, 0.5, periodic=True, out=dt)
         if ev is not None:
             ev[0].record(stream)
-        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, want_bflux=False, out=dst)
+        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, want_bflux=False, out=dst,
+                cfl=0.5, dt_next=dt)
         if ev is not None:
             ev[1].record(stream)
 
-    log("bench: autotuning the step kernel")
-    dt_host = 0.5 * dx / 8.0
-    gd.autotune_step(ua, GAMMA, dx, dt_host, periodic=True, out=ub)
+    if tile is None:
+        log("bench: autotuning the step kernel")
+        dt_host = 0.5 * dx / 8.0
+        gd.autotune_step(ua, GAMMA, dx, dt_host, periodic=True, out=ub)
+    else:
+        cfg = gd.get_config(torch.float64)
+        cfg.update(shape_single=tile, zlen_single=zlen or 16)
+        gd.set_config(torch.float64, **cfg)
     log(f"bench: config {gd.get_config(torch.float64)}")
     log(f"bench: {warmup} warmup steps")
+    gd.cfl_dt(ua, GAMMA, dx, 0.5, periodic=True, out=dt)
     for i in range(warmup):
         one_step(ua, ub) if i % 2 == 0 else one_step(ub, ua)
     torch.cuda.synchronize()
     # restart from the initial state so that every run times the same data
     ua.copy_(torch.from_numpy(u0))
+    gd.cfl_dt(ua, GAMMA, dx, 0.5, periodic=True, out=dt)
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
     torch.cuda.synchronize()
@@ -133,15 +144,20 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
     gd.cfl_dt_batched(u_in, table, GAMMA, 0.5, out=dt)
     gd.autotune_batched(u_in, table, GAMMA, out=out, bflux=flux)
     log(f"bench: batched config {gd.get_config(dtype)}")
+    # the batched step writes the batch's next CFL step into a second scalar
+    # (the input state is the same every repetition, so dt stays the same)
+    dt_next = torch.empty_like(dt)
     for _ in range(warmup):
-        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt)
+        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt, cfl=0.5,
+                        dt_next=dt_next)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     stream = torch.cuda.current_stream()
     for i in range(steps):
         ev[i][0].record(stream)
-        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt)
+        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt, cfl=0.5,
+                        dt_next=dt_next)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     ms = sum(a.elapsed_time(b) for a, b in ev) / steps
@@ -195,6 +211,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--tile", choices=["16x16", "8x8", "32x8"], default=None,
+                    help="fix the step kernel's tile shape instead of autotuning")
+    ap.add_argument("--zlen", type=int, default=None, help="z-range length with --tile")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -217,7 +236,7 @@ def main():
         torch.cuda.synchronize()
 
     torch.cuda.synchronize()
-    r = bench_periodic(torch, gd, args.steps, args.warmup)
+    r = bench_periodic(torch, gd, args.steps, args.warmup, tile=args.tile, zlen=args.zlen)
     value = r["cells"] / (r["ms_per_step"] * 1e-3) / 1e6
     achieved = r["bytes_per_launch"] / (r["step_kernel_ms"] * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -236,8 +255,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "periodic Euler box 256^3 FP64: log-normal density (sigma_ln=1, "
-                        "k^-11/3 GRF), rms Mach 2, p = 0.6 rho/gamma, gamma=5/3; per step "
-                        "cfl_dt (C=0.5, device scalar) + godunov_step, minmod + HLLC",
+                        "k^-11/3 GRF), rms Mach 2, p = 0.6 rho/gamma, gamma=5/3; per step one "
+                        "godunov_step_cfl launch (step + CFL reduction of the new state, C=0.5, "
+                        "dt in a device scalar), minmod + HLLC",
             "cells": r["cells"], "global_batch": 1, "parallelism": "none (1 GPU)",
         },
         "roofline": {

@@ -141,6 +141,22 @@ int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_
                          const void *u_in_base, void *u_out_base, void *bflux_base,
                          const double *dt_dev, double gamma, void *hip_stream);
 
+/* godunov_step / godunov_step_batched that also produce the CFL time step of
+ * the state they write: the launch reduces (|u|+|v|+|w|+3c)/dx over every
+ * interior cell it writes, and its last workgroup stores
+ * *dt_next_dev = cfl / max, the value cfl_dt would return for u_out (Sec. 4:
+ * adaptive time steps). A time loop then needs one launch per step and never
+ * reads the state a second time. dt_next_dev may be the same address as
+ * dt_dev (every workgroup reads dt before the last one writes). cfl > 0. */
+int godunov_step_cfl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                     const void *u_in, void *u_out, void *bflux, double gamma, double dx,
+                     double dt, const double *dt_dev, double cfl, double *dt_next_dev,
+                     void *hip_stream);
+int godunov_step_batched_cfl(gd_ctx *ctx, const gd_opts *opts, int npatch,
+                             const gd_patch *patches, const void *u_in_base, void *u_out_base,
+                             void *bflux_base, const double *dt_dev, double gamma, double cfl,
+                             double *dt_next_dev, void *hip_stream);
+
 /* Reverse-mode adjoint of godunov_step for a FIXED dt (dt is not
  * differentiated): given lam_out = dL/dU^{n+1} ([5][nz][ny][nx]) and
  * optionally lam_bflux = dL/dbflux (boundary-flux layout, or NULL), writes

@@ -341,9 +341,13 @@ int gd_reset_stats(gd_ctx *ctx)
     return GD_OK;
 }
 
-int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
-                 const void *u_in, void *u_out, void *bflux, double gamma, double dx, double dt,
-                 const double *dt_dev, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+              const void *u_in, void *u_out, void *bflux, double gamma, double dx, double dt,
+              const double *dt_dev, double cfl, double *dt_next, void *hip_stream)
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
@@ -358,6 +362,9 @@ int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int n
     if (overlap(u_in, nin, u_out, nout)) return fail(ctx, GD_E_ARG, "u_out overlaps u_in");
     if (bflux && (overlap(bflux, nfl, u_in, nin) || overlap(bflux, nfl, u_out, nout)))
         return fail(ctx, GD_E_ARG, "bflux overlaps u_in or u_out");
+    if (dt_next && !(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
+    if (dt_next && (overlap(dt_next, 8, u_in, nin) || overlap(dt_next, 8, u_out, nout)))
+        return fail(ctx, GD_E_ARG, "dt_next overlaps a state array");
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
 
@@ -366,16 +373,18 @@ int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int n
     P.in_off = 0; P.out_off = 0; P.flux_off = bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
     int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann,
                             ctx->shape_single[opts->dtype], P, u_in, u_out, bflux, dt_dev, sc,
-                            ctx->d_u64, ctx->zlen_single[opts->dtype], (hipStream_t)hip_stream);
+                            ctx->d_u64, ctx->zlen_single[opts->dtype], co, (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "godunov_step launch");
     return GD_OK;
 }
 
-int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
-                         const void *u_in_base, void *u_out_base, void *bflux_base,
-                         const double *dt_dev, double gamma, void *hip_stream)
+int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+                      const void *u_in_base, void *u_out_base, void *bflux_base,
+                      const double *dt_dev, double gamma, double cfl, double *dt_next,
+                      void *hip_stream)
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
@@ -397,6 +406,10 @@ int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_
     if (bflux_base && fl_end > 0 && (overlap(bflux_base, fl_end * es, u_in_base, in_end * es) ||
                                      overlap(bflux_base, fl_end * es, u_out_base, out_end * es)))
         return fail(ctx, GD_E_ARG, "bflux range overlaps u_in or u_out");
+    if (dt_next && !(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
+    if (dt_next && (overlap(dt_next, 8, u_in_base, in_end * es) ||
+                    overlap(dt_next, 8, u_out_base, out_end * es)))
+        return fail(ctx, GD_E_ARG, "dt_next overlaps a state array");
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
@@ -407,11 +420,52 @@ int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_
     int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, c.shape, ctx->device);
     int grid = std::min(c.nitems, per_cu * ctx->num_cus);
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
     int e = gd::launch_step_batched(opts->dtype, opts->limiter, opts->riemann, c.shape, c.d_patches,
                                     c.d_items, c.nitems, u_in_base, u_out_base, bflux_base, dt_dev,
-                                    sc, ctx->d_u64, ctx->d_u32, std::max(grid, 1), s);
+                                    sc, ctx->d_u64, ctx->d_u32, std::max(grid, 1), co, s);
     if (e) return hip_fail(ctx, e, "godunov_step_batched launch");
     return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                 const void *u_in, void *u_out, void *bflux, double gamma, double dx, double dt,
+                 const double *dt_dev, void *hip_stream)
+{
+    return step_impl(ctx, opts, nx, ny, nz, ng, u_in, u_out, bflux, gamma, dx, dt, dt_dev, 0.0,
+                     nullptr, hip_stream);
+}
+
+int godunov_step_cfl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
+                     const void *u_in, void *u_out, void *bflux, double gamma, double dx,
+                     double dt, const double *dt_dev, double cfl, double *dt_next_dev,
+                     void *hip_stream)
+{
+    if (!dt_next_dev) return fail(ctx, GD_E_ARG, "dt_next_dev must not be NULL");
+    return step_impl(ctx, opts, nx, ny, nz, ng, u_in, u_out, bflux, gamma, dx, dt, dt_dev, cfl,
+                     dt_next_dev, hip_stream);
+}
+
+int godunov_step_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,
+                         const void *u_in_base, void *u_out_base, void *bflux_base,
+                         const double *dt_dev, double gamma, void *hip_stream)
+{
+    return step_batched_impl(ctx, opts, npatch, patches, u_in_base, u_out_base, bflux_base, dt_dev,
+                             gamma, 0.0, nullptr, hip_stream);
+}
+
+int godunov_step_batched_cfl(gd_ctx *ctx, const gd_opts *opts, int npatch,
+                             const gd_patch *patches, const void *u_in_base, void *u_out_base,
+                             void *bflux_base, const double *dt_dev, double gamma, double cfl,
+                             double *dt_next_dev, void *hip_stream)
+{
+    if (!dt_next_dev) return fail(ctx, GD_E_ARG, "dt_next_dev must not be NULL");
+    return step_batched_impl(ctx, opts, npatch, patches, u_in_base, u_out_base, bflux_base, dt_dev,
+                             gamma, cfl, dt_next_dev, hip_stream);
 }
 
 int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches,

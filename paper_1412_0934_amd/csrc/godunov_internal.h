@@ -37,16 +37,27 @@ struct Scalars {
     double gamma, rho_floor, p_floor;
 };
 
+// Optional fused CFL output of a step launch: when dt_next is not null the
+// launch also reduces the signal speed of the state it writes and its last
+// workgroup stores dt_next = cfl / max((|u|+|v|+|w|+3c)/dx).
+struct CflOut {
+    double cfl;
+    double *dt_next;
+    unsigned long long *smax_bits;
+    unsigned *done;
+};
+
 // Launchers. Return 0 or a hipError_t value.
 int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,
-                const Scalars &sc, unsigned long long *hits, int zlen, hipStream_t s);
+                const Scalars &sc, unsigned long long *hits, int zlen, const CflOut &co,
+                hipStream_t s);
 
 int launch_step_batched(int dtype, int limiter, int riemann, int shape,
                         const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
                         const void *u_in, void *u_out, void *bflux, const double *dt_dev,
                         const Scalars &sc, unsigned long long *hits, unsigned *d_queue,
-                        int grid, hipStream_t s);
+                        int grid, const CflOut &co, hipStream_t s);
 
 // Work item of the CFL reduction: rows [j0, j0+nrow) of plane k of a patch.
 struct CflItem {

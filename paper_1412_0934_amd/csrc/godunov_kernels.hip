@@ -298,6 +298,58 @@ __device__ __forceinline__ void load5(const T *__restrict__ p, int64_t vstride, 
     for (int q = 0; q < 5; ++q) U[q] = p[q * vstride];
 }
 
+// ------------------------------------------------------------ CFL reduction
+
+// |u| + |v| + |w| + 3c of a conserved state, c = sqrt(g p / rho) evaluated as
+// g p / sqrt(g p rho). The CFL kernels and the fused CFL of the step kernels
+// share this function, so both give the same dt bit for bit.
+template <typename T>
+__device__ __forceinline__ double cell_signal(const T U[5], const Phys<T> &ph, int &hits)
+{
+    T W[5], inv;
+    prim_from_cons(U, W, inv, ph, hits);
+    T gp = ph.gamma * W[4];
+    T c = gp * fast_rsqrt(gp * W[0]);
+    return (double)(fabs(W[1]) + fabs(W[2]) + fabs(W[3]) + T(3) * c);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide max of v (>= 0) folded into *smax_bits, the bit pattern of a
+// non-negative double (which orders like the value). Thread 0 reads the
+// running value first and issues the device-wide atomic only when the
+// block's maximum exceeds it, so a grid of thousands of workgroups performs
+// few same-address atomics. A one-thread launch (cfl_finalize_kernel) then
+// turns the maximum into dt and clears it for the next use.
+__device__ void cfl_block_max(double v, unsigned long long *smax_bits)
+{
+    __shared__ double part[16];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) m = fmax(m, part[i]);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(m);
+        if (b > __atomic_load_n(smax_bits, __ATOMIC_RELAXED)) atomicMax(smax_bits, b);
+    }
+}
+
+__global__ __launch_bounds__(64) void cfl_finalize_kernel(double cfl, double *dt_out,
+                                                          unsigned long long *smax_bits)
+{
+    if (threadIdx.x == 0) {
+        const unsigned long long b = atomicExch(smax_bits, 0ull);
+        *dt_out = cfl / __longlong_as_double((long long)b);
+    }
+}
+
 // ------------------------------------------------------------ the tile march
 
 template <typename T, int TX, int TY>
@@ -332,7 +384,7 @@ template <typename T, int LIM, int RS, int TX, int TY>
 __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
                              T *__restrict__ u_out_base, T *__restrict__ bflux_base, T dtdx, T lam,
                              const Phys<T> &ph, int x0, int y0, int z0, int z1,
-                             TileSmem<T, TX, TY> &sm, int &hits)
+                             TileSmem<T, TX, TY> &sm, int &hits, bool want_cfl, double &smax)
 {
     using Geo = TileGeom<TX, TY>;
     constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX;
@@ -386,6 +438,7 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
 
     T *__restrict__ out = u_out_base + P.out_off;
     const int64_t ostride = (int64_t)P.nx * P.ny * P.nz;
+    const double inv_dx = 1.0 / P.dx;
     const int64_t ocol = (int64_t)gj * P.nx + gi;
 
     // ---- registers of the owned column
@@ -397,8 +450,17 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
         zprev[q] = acc[q] = zm[q] = zpn[q] = T(0);
     }
 
-    // prologue: plane z0-2 (interior only, straight into its LDS buffer) and
-    // plane z0-1 (into the column registers)
+    // Column loads run one plane ahead of their use: the raw conserved state
+    // of plane k+1 (Upf) and of the halo of plane k (Hpf) are in flight while
+    // plane k-1 is computed. The last plane a column reads is z1+1 for an
+    // interior column and z1 for a ring column.
+    const int last_plane = interior ? z1 + 1 : z1;
+    T Upf[5], Hpf[5], Uold[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Upf[q] = Hpf[q] = Uold[q] = T(0);
+
+    // prologue: plane z0-2 (interior only, straight into its LDS buffer),
+    // plane z0-1 (into the column registers) and the loads of plane z0
     if (owner) {
         T U[5], Wt[5], inv;
         if (interior) {
@@ -409,7 +471,9 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
         }
         load5(uin + view.plane(z0 - 1) + col, view.vstride, U);
         prim_from_cons(U, Wp, invp, ph, hits);
+        load5(uin + view.plane(z0) + col, view.vstride, Upf);
     }
+    if (halo) load5(uin + view.plane(z0) + hcol, view.vstride, Hpf);
 
     const int lx = ci + 2, ly = cj + 2;
     const T half = T(0.5);
@@ -422,21 +486,20 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
 #pragma unroll
         for (int q = 0; q < 5; ++q) W0[q] = Wp[q];
         inv0 = invp;
-        if (interior || (owner && !post)) {
-            T U[5];
-            load5(uin + view.plane(k + 1) + col, view.vstride, U);
-            prim_from_cons(U, Wp, invp, ph, hits);
+        if (owner && k + 1 <= last_plane) {
+            prim_from_cons(Upf, Wp, invp, ph, hits);
+            if (k + 2 <= last_plane) load5(uin + view.plane(k + 2) + col, view.vstride, Upf);
         }
         if (owner) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) sm.w[cur][q][ly][lx] = W0[q];
         }
         if (!pre && !post && halo) {
-            T U[5], Wh[5], invh;
-            load5(uin + view.plane(k) + hcol, view.vstride, U);
-            prim_from_cons(U, Wh, invh, ph, hits);
+            T Wh[5], invh;
+            prim_from_cons(Hpf, Wh, invh, ph, hits);
 #pragma unroll
             for (int q = 0; q < 5; ++q) sm.w[cur][q][hj + 2][hi + 2] = Wh[q];
+            if (k + 1 < z1) load5(uin + view.plane(k + 1) + hcol, view.vstride, Hpf);
         }
         __syncthreads();
 
@@ -483,6 +546,8 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                     face_state(Ws, Sz, half, zpn, ph, hits);
                 }
             }
+            // the conserved state of plane k-1, completed in phase C2
+            if (interior && k > z0) load5(uin + view.plane(k - 1) + col, view.vstride, Uold);
         }
         if (!post) __syncthreads();
         if (pre) continue;
@@ -542,11 +607,18 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
             }
             if (k > z0) {
                 // U' = U - dt/dx (acc + F_z(k-1/2)), acc = div_xy(k-1) - F_z(k-3/2)
-                T U[5];
-                load5(uin + view.plane(k - 1) + col, view.vstride, U);
                 T *o = out + (int64_t)(k - 1) * P.nx * P.ny + ocol;
+                T Un[5];
 #pragma unroll
-                for (int q = 0; q < 5; ++q) o[q * ostride] = U[q] - dtdx * (acc[q] + F[q]);
+                for (int q = 0; q < 5; ++q) {
+                    Un[q] = Uold[q] - dtdx * (acc[q] + F[q]);
+                    o[q * ostride] = Un[q];
+                }
+                if (want_cfl) {
+                    // signal speed of the new state, exactly as cfl_dt computes it
+                    int unused = 0;
+                    smax = fmax(smax, cell_signal(Un, ph, unused) * inv_dx);
+                }
             }
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
@@ -588,11 +660,16 @@ __device__ __forceinline__ void flush_hits(int hits, unsigned long long *counter
 // with its own L2); the block index is remapped so that each XCD works
 // through a contiguous range of items, ordered z-segment-major then tile
 // row-major, so that tiles sharing halo columns run on the same L2.
+// Occupancy target: three waves per SIMD in FP64 (168 VGPRs), four in FP32.
+template <typename T>
+constexpr int waves_per_eu() { return sizeof(T) == 8 ? 3 : 4; }
+
 template <typename T, int LIM, int RS, int TX, int TY>
-__global__ __launch_bounds__(tile_threads(TX, TY)) void step_kernel(
+__global__ __launch_bounds__(tile_threads(TX, TY))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_kernel(
     PatchDesc P, const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ bflux,
-    const double *__restrict__ dt_dev, Scalars sc, unsigned long long *hits_ctr, int ntx, int nty,
-    int zlen)
+    const double *dt_dev, Scalars sc, unsigned long long *hits_ctr, int ntx, int nty, int zlen,
+    CflOut co)
 {
     __shared__ TileSmem<T, TX, TY> sm;
     const Phys<T> ph = make_phys<T>(sc);
@@ -607,8 +684,12 @@ __global__ __launch_bounds__(tile_threads(TX, TY)) void step_kernel(
     const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
     const int z0 = seg * zlen, z1 = min(z0 + zlen, P.nz);
     int hits = 0;
-    godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, x0, y0, z0, z1, sm, hits);
+    double smax = 0.0;
+    const bool want_cfl = co.dt_next != nullptr;
+    godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, x0, y0, z0, z1, sm, hits,
+                                     want_cfl, smax);
     flush_hits(hits, hits_ctr);
+    if (want_cfl) cfl_block_max(smax, co.smax_bits);
 }
 
 // A batch: a persistent grid; each workgroup pulls (patch, tile, z-range)
@@ -616,15 +697,18 @@ __global__ __launch_bounds__(tile_threads(TX, TY)) void step_kernel(
 // workgroup to leave resets the counter, so the next launch (or graph replay)
 // starts from zero without a separate reset.
 template <typename T, int LIM, int RS, int TX, int TY>
-__global__ __launch_bounds__(tile_threads(TX, TY)) void step_batched_kernel(
+__global__ __launch_bounds__(tile_threads(TX, TY))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_batched_kernel(
     const PatchDesc *__restrict__ patches, const WorkItem *__restrict__ items, int nitems,
     const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ bflux,
-    const double *__restrict__ dt_dev, Scalars sc, unsigned long long *hits_ctr, unsigned *queue)
+    const double *dt_dev, Scalars sc, unsigned long long *hits_ctr, unsigned *queue, CflOut co)
 {
     __shared__ TileSmem<T, TX, TY> sm;
     __shared__ int s_item;
     const Phys<T> ph = make_phys<T>(sc);
     int hits = 0;
+    double smax = 0.0;
+    const bool want_cfl = co.dt_next != nullptr;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
         __syncthreads();
@@ -636,59 +720,17 @@ __global__ __launch_bounds__(tile_threads(TX, TY)) void step_batched_kernel(
         const double dt = dt_dev ? *dt_dev : P.dt;
         const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
         godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0,
-                                         w.z1, sm, hits);
+                                         w.z1, sm, hits, want_cfl, smax);
         __syncthreads();
     }
     flush_hits(hits, hits_ctr);
+    if (want_cfl) cfl_block_max(smax, co.smax_bits);
     if (threadIdx.x == 0) {
         __threadfence();
         unsigned done = atomicAdd(&queue[1], 1u);
         if (done == gridDim.x - 1) {
             atomicExch(&queue[0], 0u);
             atomicExch(&queue[1], 0u);
-        }
-    }
-}
-
-// ------------------------------------------------------------ CFL reduction
-
-template <typename T>
-__device__ __forceinline__ double cell_signal(const T U[5], const Phys<T> &ph, int &hits)
-{
-    T W[5], inv;
-    prim_from_cons(U, W, inv, ph, hits);
-    T c = sqrt(ph.gamma * W[4] / W[0]);
-    return (double)(fabs(W[1]) + fabs(W[2]) + fabs(W[3]) + T(3) * c);
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Block-wide max of v (>= 0) folded into *smax_bits; the last block turns it
-// into dt = cfl / smax and resets the accumulators.
-__device__ void cfl_finish(double v, double cfl, double *dt_out, unsigned long long *smax_bits,
-                           unsigned *done)
-{
-    __shared__ double part[16];
-    v = wave_max(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) part[wv] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) m = fmax(m, part[i]);
-        atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
-        __threadfence();
-        unsigned t = atomicAdd(done, 1u);
-        if (t == gridDim.x - 1) {
-            unsigned long long b = atomicAdd(smax_bits, 0ull);
-            *dt_out = cfl / __longlong_as_double((long long)b);
-            atomicExch(smax_bits, 0ull);
-            atomicExch(done, 0u);
         }
     }
 }
@@ -718,7 +760,10 @@ __global__ __launch_bounds__(256) void cfl_kernel(const PatchDesc *__restrict__ 
         }
     }
     (void)hits_ctr;
-    cfl_finish(vmax, cfl, dt_out, smax_bits, done);
+    (void)cfl;
+    (void)dt_out;
+    (void)done;
+    cfl_block_max(vmax, smax_bits);
 }
 
 template <typename T>
@@ -743,7 +788,10 @@ __global__ __launch_bounds__(256) void cfl_single_kernel(PatchDesc P, const T *_
         load5(base + view.plane(k) + view.column(i, j), view.vstride, U);
         vmax = fmax(vmax, cell_signal(U, ph, hits) * inv_dx);
     }
-    cfl_finish(vmax, cfl, dt_out, smax_bits, done);
+    (void)cfl;
+    (void)dt_out;
+    (void)done;
+    cfl_block_max(vmax, smax_bits);
 }
 
 // ------------------------------------------------------------ launchers
@@ -751,7 +799,7 @@ __global__ __launch_bounds__(256) void cfl_single_kernel(PatchDesc P, const T *_
 template <typename T, int LIM, int RS, int TX, int TY>
 static int launch_step_t(const PatchDesc &P, const void *u_in, void *u_out, void *bflux,
                          const double *dt_dev, const Scalars &sc, unsigned long long *hits,
-                         int zlen, hipStream_t s)
+                         int zlen, const CflOut &co, hipStream_t s)
 {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     const int nseg = (P.nz + zlen - 1) / zlen;
@@ -759,7 +807,10 @@ static int launch_step_t(const PatchDesc &P, const void *u_in, void *u_out, void
     if (nblocks <= 0 || nblocks > 0x7fffffff) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL((step_kernel<T, LIM, RS, TX, TY>), dim3((unsigned)nblocks),
                        dim3(TileGeom<TX, TY>::NT), 0, s, P, (const T *)u_in, (T *)u_out, (T *)bflux,
-                       dt_dev, sc, hits, ntx, nty, zlen);
+                       dt_dev, sc, hits, ntx, nty, zlen, co);
+    if (co.dt_next)
+        hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, co.cfl, co.dt_next,
+                           co.smax_bits);
     return (int)hipGetLastError();
 }
 
@@ -767,23 +818,27 @@ template <typename T, int LIM, int RS, int TX, int TY>
 static int launch_batched_t(const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
                             const void *u_in, void *u_out, void *bflux, const double *dt_dev,
                             const Scalars &sc, unsigned long long *hits, unsigned *d_queue,
-                            int grid, hipStream_t s)
+                            int grid, const CflOut &co, hipStream_t s)
 {
     hipLaunchKernelGGL((step_batched_kernel<T, LIM, RS, TX, TY>), dim3(grid),
                        dim3(TileGeom<TX, TY>::NT), 0, s, d_patches, d_items, nitems,
-                       (const T *)u_in, (T *)u_out, (T *)bflux, dt_dev, sc, hits, d_queue);
+                       (const T *)u_in, (T *)u_out, (T *)bflux, dt_dev, sc, hits, d_queue, co);
+    if (co.dt_next)
+        hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, co.cfl, co.dt_next,
+                           co.smax_bits);
     return (int)hipGetLastError();
 }
 
 template <typename T, int LIM, int RS>
 static int dispatch_shape_step(int shape, const PatchDesc &P, const void *u_in, void *u_out,
                                void *bflux, const double *dt_dev, const Scalars &sc,
-                               unsigned long long *hits, int zlen, hipStream_t s)
+                               unsigned long long *hits, int zlen, const CflOut &co,
+                               hipStream_t s)
 {
     switch (shape) {
-    case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, s);
-    case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, s);
-    default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, s);
+    case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
     }
 }
 
@@ -792,12 +847,12 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
                                   int nitems, const void *u_in, void *u_out, void *bflux,
                                   const double *dt_dev, const Scalars &sc,
                                   unsigned long long *hits, unsigned *d_queue, int grid,
-                                  hipStream_t s)
+                                  const CflOut &co, hipStream_t s)
 {
     switch (shape) {
-    case TILE_8x8: return launch_batched_t<T, LIM, RS, 8, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, s);
-    case TILE_32x8: return launch_batched_t<T, LIM, RS, 32, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, s);
-    default: return launch_batched_t<T, LIM, RS, 16, 16>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, s);
+    case TILE_8x8: return launch_batched_t<T, LIM, RS, 8, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    case TILE_32x8: return launch_batched_t<T, LIM, RS, 32, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    default: return launch_batched_t<T, LIM, RS, 16, 16>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     }
 }
 
@@ -815,22 +870,23 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
 
 int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,
-                const Scalars &sc, unsigned long long *hits, int zlen, hipStream_t s)
+                const Scalars &sc, unsigned long long *hits, int zlen, const CflOut &co,
+                hipStream_t s)
 {
     if (dtype == 1)
-        GD_DISPATCH_SCHEME(dispatch_shape_step, float, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, s);
-    GD_DISPATCH_SCHEME(dispatch_shape_step, double, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, s);
+        GD_DISPATCH_SCHEME(dispatch_shape_step, float, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    GD_DISPATCH_SCHEME(dispatch_shape_step, double, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
 }
 
 int launch_step_batched(int dtype, int limiter, int riemann, int shape,
                         const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
                         const void *u_in, void *u_out, void *bflux, const double *dt_dev,
                         const Scalars &sc, unsigned long long *hits, unsigned *d_queue, int grid,
-                        hipStream_t s)
+                        const CflOut &co, hipStream_t s)
 {
     if (dtype == 1)
-        GD_DISPATCH_SCHEME(dispatch_shape_batched, float, shape, d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, s);
-    GD_DISPATCH_SCHEME(dispatch_shape_batched, double, shape, d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, s);
+        GD_DISPATCH_SCHEME(dispatch_shape_batched, float, shape, d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    GD_DISPATCH_SCHEME(dispatch_shape_batched, double, shape, d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
 }
 
 int launch_cfl(int dtype, const PatchDesc *d_patches, const CflItem *d_items, int nitems,
@@ -843,6 +899,7 @@ int launch_cfl(int dtype, const PatchDesc *d_patches, const CflItem *d_items, in
     else
         hipLaunchKernelGGL(cfl_kernel<double>, dim3(grid), dim3(256), 0, s, d_patches, d_items,
                            nitems, (const double *)u, sc, cfl, dt_out, smax_bits, done, nullptr);
+    hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, cfl, dt_out, smax_bits);
     return (int)hipGetLastError();
 }
 
@@ -860,6 +917,7 @@ int launch_cfl_single(int dtype, const PatchDesc &P, const void *u, const Scalar
     else
         hipLaunchKernelGGL(cfl_single_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, P,
                            (const double *)u, sc, cfl, dt_out, smax_bits, done);
+    hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, cfl, dt_out, smax_bits);
     return (int)hipGetLastError();
 }
 

@@ -59,7 +59,8 @@ assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
 
 EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
            "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt",
-           "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config")
+           "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
+           "godunov_step_cfl", "godunov_step_batched_cfl")
 
 _lib = None
 _lock = threading.Lock()
@@ -88,6 +89,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.godunov_step_adjoint.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, vp, vp,
                                              dbl, dbl, dbl, vp]
         lib.cfl_dt.argtypes = [vp, P(gd_opts), i32, vp, vp, dbl, dbl, vp, vp]
+        lib.godunov_step_cfl.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, vp, dbl, dbl,
+                                         dbl, vp, dbl, vp, vp]
+        lib.godunov_step_batched_cfl.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, vp, dbl, dbl,
+                                                 vp, vp]
         ip = P(ctypes.c_int)
         lib.gd_autotune_step.argtypes = [vp, P(gd_opts), i32, i32, i32, i32, vp, vp, dbl, dbl, dbl,
                                          vp, ip]
@@ -186,8 +191,10 @@ def interior_shape(u, ng, periodic):
 
 def step(u, gamma, dx, dt=None, *, dt_dev=None, ng=2, periodic=False, limiter="minmod",
          riemann="hllc", want_bflux=True, out=None, bflux=None, rho_floor=RHO_FLOOR,
-         p_floor=P_FLOOR, stream=None):
-    """One Godunov step of one patch. Returns (u_new [5,nz,ny,nx], bflux or None)."""
+         p_floor=P_FLOOR, stream=None, cfl=None, dt_next=None):
+    """One Godunov step of one patch. Returns (u_new [5,nz,ny,nx], bflux or None).
+    With cfl and dt_next (a 1-element float64 device tensor, which may be
+    dt_dev itself) the launch also writes the CFL step of u_new to dt_next."""
     _check_tensor(u, "u")
     nx, ny, nz = interior_shape(u, ng, periodic)
     if out is None:
@@ -203,6 +210,14 @@ def step(u, gamma, dx, dt=None, *, dt_dev=None, ng=2, periodic=False, limiter="m
         raise ValueError("give dt or dt_dev")
     ctx = context(u.device.index)
     o = _opts(u.dtype, periodic, limiter, riemann, rho_floor, p_floor)
+    if dt_next is not None:
+        _check_tensor(dt_next, "dt_next", torch.float64)
+        ctx.check(ctx.lib.godunov_step_cfl(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u),
+                                           _ptr(out), _ptr(bflux), float(gamma), float(dx),
+                                           float(dt if dt is not None else 0.0), _ptr(dt_dev),
+                                           float(0.5 if cfl is None else cfl), _ptr(dt_next),
+                                           _stream(stream)))
+        return out, bflux
     ctx.check(ctx.lib.godunov_step(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u), _ptr(out),
                                    _ptr(bflux), float(gamma), float(dx),
                                    float(dt if dt is not None else 0.0), _ptr(dt_dev),
@@ -242,8 +257,10 @@ def patch_table(dims, ng, u_in_off, u_out_off, flux_off, dx, dt=0.0) -> np.ndarr
 
 
 def step_batched(u_in, table, gamma, *, out, bflux=None, dt_dev=None, limiter="minmod",
-                 riemann="hllc", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None):
-    """One step of every patch in `table` (see patch_table), one launch."""
+                 riemann="hllc", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None, cfl=None,
+                 dt_next=None):
+    """One step of every patch in `table` (see patch_table), one launch.
+    With cfl and dt_next the launch also writes the batch's next CFL step."""
     _check_tensor(u_in, "u_in")
     _check_tensor(out, "out", u_in.dtype)
     if bflux is not None:
@@ -253,6 +270,13 @@ def step_batched(u_in, table, gamma, *, out, bflux=None, dt_dev=None, limiter="m
     table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
     ctx = context(u_in.device.index)
     o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
+    if dt_next is not None:
+        _check_tensor(dt_next, "dt_next", torch.float64)
+        ctx.check(ctx.lib.godunov_step_batched_cfl(
+            ctx.handle, ctypes.byref(o), len(table), table.ctypes.data, _ptr(u_in), _ptr(out),
+            _ptr(bflux), _ptr(dt_dev), float(gamma), float(0.5 if cfl is None else cfl),
+            _ptr(dt_next), _stream(stream)))
+        return out, bflux
     ctx.check(ctx.lib.godunov_step_batched(ctx.handle, ctypes.byref(o), len(table),
                                            table.ctypes.data, _ptr(u_in), _ptr(out), _ptr(bflux),
                                            _ptr(dt_dev), float(gamma), _stream(stream)))

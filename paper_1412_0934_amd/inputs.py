@@ -119,21 +119,24 @@ def _random_unit(rng):
     return v / np.linalg.norm(v)
 
 
-def _random_wavevector(rng, kmax):
+def _random_wavevector(rng, kmax, generic=False):
+    """Integer wavevector in [-kmax, kmax]^3, not zero; with generic=True no
+    component is zero (the field then varies along every axis)."""
     while True:
         k = rng.integers(-kmax, kmax + 1, size=3)
-        if np.any(k != 0):
+        if np.all(k != 0) if generic else np.any(k != 0):
             return k.astype(np.float64)
 
 
-def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0, out=None):
+def shocked_patch(rng, nx, ny, nz, ng=2, dx=1.0 / 256, gamma=GAMMA, mach=3.0, out=None,
+                  generic=False):
     """One ghost-zoned patch (5, nz+2ng, ny+2ng, nx+2ng): smooth sine background
     (rho and p at 1 +- 0.2, |v| <= 0.1) evaluated at cell centres from a random
     origin, cut by a planar shock of random normal through a random interior
     point. The post-shock side carries the Rankine-Hugoniot state of a Mach
     `mach` shock relative to the local background."""
     origin = rng.uniform(0.0, 1.0, size=3)
-    kr, kp, kv = (_random_wavevector(rng, 2) for _ in range(3))
+    kr, kp, kv = (_random_wavevector(rng, 2, generic) for _ in range(3))
     phr, php, phv = rng.uniform(0.0, 2 * math.pi, size=3)
     ev = _random_unit(rng)
     normal = _random_unit(rng)
@@ -255,10 +258,29 @@ def amr_batch(npatch=4096, seed=5, ng=2, dx=1.0 / 256, gamma=GAMMA,
     return batch
 
 
-def random_patch(nx, ny, nz, ng=2, seed=0, dx=None, gamma=GAMMA, mach=3.0):
-    """Generic test patch: the shocked_patch field of the given extents."""
+def random_patch(nx, ny, nz, ng=2, seed=0, dx=None, gamma=GAMMA, mach=3.0, generic=False):
+    """Test patch: the shocked_patch field of the given extents. generic=True
+    draws background waves that vary along every axis, so that no primitive
+    is constant along an axis (whose slopes would be pure rounding noise)."""
     rng = np.random.default_rng(seed)
-    return shocked_patch(rng, nx, ny, nz, ng, 1.0 / 64 if dx is None else dx, gamma, mach)
+    return shocked_patch(rng, nx, ny, nz, ng, 1.0 / 64 if dx is None else dx, gamma, mach,
+                         generic=generic)
+
+
+def smooth_direction(shape, seed, nmodes=4, kmax=3):
+    """A smooth random perturbation field (each of the 5 variables a sum of
+    low Fourier modes with N(0,1) amplitudes), for directional derivatives."""
+    rng = np.random.default_rng(seed)
+    n = shape[-1]
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    out = np.zeros(shape)
+    for v in range(shape[0]):
+        for _ in range(nmodes):
+            k = _random_wavevector(rng, kmax)
+            out[v] += rng.standard_normal() * np.sin(2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z)
+                                                     + rng.uniform(0, 2 * math.pi))
+    return out
 
 
 def _mode_sum(n, rng, nmodes=8, kmax=4):

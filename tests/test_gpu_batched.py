@@ -150,3 +150,26 @@ def test_full_amr_batch(gd, amr, dtype_name):
                       (("x+", 1), ("x-", -1), ("y+", 1), ("y-", -1), ("z+", 1), ("z-", -1)))
             scale = math.fsum(np.abs(before[v]).ravel())
             assert abs(lhs + dt / amr.dx[p] * net) <= 1e-12 * scale, (p, v)
+
+
+def test_fused_cfl_batched_step(gd):
+    """godunov_step_batched_cfl writes the same states as the plain batched
+    step and dt_next = min over patches of C dx_p / s_p of the new states."""
+    import torch
+    batch = small_batch(seed=25)
+    table = gd.patch_table(batch.dims, batch.ng, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, 0.0)
+    u_in = torch.from_numpy(batch.u_in).cuda()
+    dt = gd.cfl_dt_batched(u_in, table, G, 0.5)
+    out1 = torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda")
+    out2 = torch.empty_like(out1)
+    say("fused batched: plain")
+    gd.step_batched(u_in, table, G, out=out1, dt_dev=dt)
+    nxt = torch.empty(1, dtype=torch.float64, device="cuda")
+    say("fused batched: with cfl")
+    gd.step_batched(u_in, table, G, out=out2, dt_dev=dt, cfl=0.5, dt_next=nxt)
+    o1, o2 = host(out1), host(out2)
+    assert np.array_equal(o1, o2)
+    ref = min(0.5 * batch.dx[p] / oracle.max_signal(batch.patch_out(o1, p), G, periodic=True)
+              for p in range(batch.npatch))
+    assert abs(float(host(nxt)[0]) - ref) <= 1e-14 * ref

@@ -223,3 +223,39 @@ def test_ten_step_periodic_rollout_with_device_dt(gd):
         gd.cfl_dt(ud, G, dx, 0.5, periodic=True, out=dt_dev)
         ud, _ = gd.step(ud, G, dx, dt_dev=dt_dev, periodic=True, want_bflux=False)
     assert rel_norm_err(host(ud), ref) <= TOL64
+
+
+def test_fused_cfl_step_matches_separate_calls(gd):
+    """godunov_step_cfl writes the same state as godunov_step and the same
+    dt as cfl_dt on that state, bit for bit; dt_next may alias dt_dev."""
+    import torch
+    n = 40
+    u = inputs.turbulent_box(n, mach=2.0)
+    dx = 1 / n
+    ud = dev(u)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.cfl_dt(ud, G, dx, 0.5, periodic=True, out=dt)
+    say("fused cfl: separate calls")
+    a, _ = gd.step(ud, G, dx, dt_dev=dt, periodic=True, want_bflux=False)
+    dta = gd.cfl_dt(a, G, dx, 0.5, periodic=True)
+    say("fused cfl: one launch")
+    nxt = torch.empty(1, dtype=torch.float64, device="cuda")
+    b, _ = gd.step(ud, G, dx, dt_dev=dt, periodic=True, want_bflux=False, cfl=0.5, dt_next=nxt)
+    assert np.array_equal(host(a), host(b))
+    assert np.array_equal(host(dta), host(nxt))
+    ref = oracle.cfl_dt(host(a), G, dx, 0.5, periodic=True)
+    assert abs(float(host(nxt)[0]) - ref) <= 1e-14 * ref
+    say("fused cfl: aliased dt")
+    c, _ = gd.step(ud, G, dx, dt_dev=dt, periodic=True, want_bflux=False, cfl=0.5, dt_next=dt)
+    assert np.array_equal(host(a), host(c)) and np.array_equal(host(dt), host(nxt))
+    # ghosted patch, with boundary fluxes
+    ug = inputs.random_patch(21, 18, 26, seed=8)
+    dxg = 1 / 64
+    dtg = oracle.cfl_dt(ug, G, dxg)
+    say("fused cfl: ghosted")
+    nx2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    o1, f1 = gd.step(dev(ug), G, dxg, dtg)
+    o2, f2 = gd.step(dev(ug), G, dxg, dtg, cfl=0.5, dt_next=nx2)
+    assert np.array_equal(host(o1), host(o2)) and np.array_equal(host(f1), host(f2))
+    ref = oracle.cfl_dt(host(o1), G, dxg, 0.5, periodic=True)
+    assert abs(float(host(nx2)[0]) - ref) <= 1e-14 * ref
