@@ -18,7 +18,11 @@ Prints one JSON line:
             FP64 and FP32, one persistent launch per step) for the
             plain-vs-batched comparison
 
+  also.adjoint  one adjoint step against one forward step (128^3), and the
+            backward pass of a checkpointed 20-step rollout against its forward
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+                       [--no-adjoint] [--tile 8x8 --zlen 16] [--calibrate-copy]
 """
 from __future__ import annotations
 
@@ -45,9 +49,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(tile_config=None):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current kernel source and the same tile
+    configuration; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -56,6 +61,8 @@ def measured_traffic():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if tile_config is not None and vals.get("tile_config") != tile_config:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -180,7 +187,61 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
 bench_batched.cache = None
 
 
-def cpu_baseline(u0, budget_s=12.0, max_steps=4):
+def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
+    """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
+    5% amplitude), fixed dt: one adjoint step against one forward step, and
+    the backward pass of a 20-step rollout with checkpoints every 5 steps
+    (segments recomputed) against its forward pass."""
+    from paper_1412_0934_amd import inputs
+    log(f"bench: adjoint, {n}^3 smooth box")
+    U0, target = inputs.smooth_box(n)
+    u0 = torch.from_numpy(U0).cuda()
+    dx = 1.0 / n
+    dt = float(gd.cfl_dt(u0, GAMMA, dx, 0.5, periodic=True).item())
+    lam = torch.randn_like(u0)
+    out = torch.empty_like(u0)
+    lin = torch.empty_like(u0)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    fwd = timed(lambda: gd.step(u0, GAMMA, dx, dt, periodic=True, want_bflux=False, out=out), steps)
+    adj = timed(lambda: gd.step_adjoint(u0, lam, GAMMA, dx, dt, periodic=True, out=lin), steps)
+    tgt = torch.from_numpy(target).cuda()
+
+    def rollout_fwd():
+        return gd.rollout(u0.requires_grad_(True), GAMMA, dx, dt, nsteps, every)
+
+    uT = rollout_fwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uT = rollout_fwd()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    loss = ((uT[0] - tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    u0.requires_grad_(False)
+    return {"workload": f"{n}^3 periodic smooth box, fixed dt, minmod + HLLC, FP64",
+            "forward_step_ms": fwd, "adjoint_step_ms": adj, "adjoint_over_forward": adj / fwd,
+            "rollout": f"{nsteps} steps, checkpoint every {every}",
+            "rollout_forward_ms": 1e3 * t_fwd, "rollout_backward_ms": 1e3 * t_bwd,
+            "rollout_backward_over_forward": t_bwd / t_fwd}
+
+
+def cpu_baseline(u0, budget_s=12.0, max_steps=40):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = u0.shape[1]
@@ -209,6 +270,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8"], default=None,
@@ -239,7 +301,8 @@ def main():
     r = bench_periodic(torch, gd, args.steps, args.warmup, tile=args.tile, zlen=args.zlen)
     value = r["cells"] / (r["ms_per_step"] * 1e-3) / 1e6
     achieved = r["bytes_per_launch"] / (r["step_kernel_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic()
+    cfg = gd.get_config(torch.float64)
+    traffic = measured_traffic(f"{cfg['shape_single']}/{cfg['zlen_single']}")
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -269,9 +332,14 @@ def main():
             "algorithmic_bytes_per_launch": r["bytes_per_launch"],
         },
     }
+    also = {}
     if not args.no_batched:
-        line["also"] = {"batched": [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
-                                    bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]}
+        also["batched"] = [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
+                           bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]
+    if not args.no_adjoint:
+        also["adjoint"] = bench_adjoint(torch, gd)
+    if also:
+        line["also"] = also
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["u0"])
     print(json.dumps(line), flush=True)
