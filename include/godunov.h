@@ -187,8 +187,9 @@ int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches
  * of a few launches per candidate), keeps the fastest in ctx for later calls
  * of the same dtype, and returns its index in *choice (may be NULL). The
  * outputs are overwritten; the stream is synchronised. Candidates: tiles of
- * 16x16, 32x8 and 8x8 interior columns; z-ranges of 16, 32 and 64 planes
- * (single patch) or of 8 planes, 16 planes and the whole patch (batched). */
+ * 16x16, 32x8, 8x8, 12x12 and 24x8 interior columns; z-ranges of 16, 32 and
+ * 64 planes (single patch) or of 8 planes, 16 planes and the whole patch
+ * (batched). */
 int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
                      const void *u_in, void *u_out, double gamma, double dx, double dt,
                      void *hip_stream, int *choice);
@@ -196,14 +197,15 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
                         const void *u_in_base, void *u_out_base, void *bflux_base, double gamma,
                         void *hip_stream, int *choice);
 
-/* The configuration in use: tile shape index (0: 16x16, 1: 8x8, 2: 32x8)
+/* The configuration in use: tile shape index (0: 16x16, 1: 8x8, 2: 32x8,
+ * 3: 12x12, 4: 24x8)
  * and z-range length (single patch) or z-range policy (batched: 0 = 8
  * planes, 1 = 16, 2 = whole patch) for dtype. */
 int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
                   int *shape_batched, int *zpolicy_batched);
 
 /* Set the configuration explicitly (e.g. one stored from an earlier
- * autotuning run). shape in {0, 1, 2}; zlen_single in [1, 4096];
+ * autotuning run). shape in [0, 4]; zlen_single in [1, 4096];
  * zpolicy_batched in {0, 1, 2}. The choice never changes results: every
  * face flux and every update is evaluated by the same arithmetic whatever
  * the tiling, so outputs are bitwise identical across configurations. */

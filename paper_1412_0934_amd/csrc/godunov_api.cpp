@@ -587,12 +587,13 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
     int r;
     if ((r = check_opts(ctx, opts))) return r;
     const int dt_i = opts->dtype;
-    const int shapes[3] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8 };
+    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
+                            gd::TILE_24x8 };
     const int zlens[3] = { 16, 32, 64 };
     const int keep_shape = ctx->shape_single[dt_i], keep_zlen = ctx->zlen_single[dt_i];
     float best = 1e30f;
     int best_i = -1;
-    for (int si = 0; si < 3; ++si)
+    for (int si = 0; si < 5; ++si)
         for (int zi = 0; zi < 3; ++zi) {
             ctx->shape_single[dt_i] = shapes[si];
             ctx->zlen_single[dt_i] = zlens[zi];
@@ -622,11 +623,12 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     int r;
     if ((r = check_opts(ctx, opts))) return r;
     const int dt_i = opts->dtype;
-    const int shapes[3] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8 };
+    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
+                            gd::TILE_24x8 };
     const int keep_shape = ctx->shape_batched[dt_i], keep_pol = ctx->zpolicy_batched[dt_i];
     float best = 1e30f;
     int best_i = -1;
-    for (int si = 0; si < 3; ++si)
+    for (int si = 0; si < 5; ++si)
         for (int zp = 0; zp < 3; ++zp) {
             ctx->shape_batched[dt_i] = shapes[si];
             ctx->zpolicy_batched[dt_i] = zp;

@@ -26,21 +26,38 @@ namespace gd {
 enum { LIM_MINMOD = 0, LIM_MC = 1, LIM_NONE = 2 };
 enum { RS_HLLC = 0, RS_HLL = 1 };
 
-int tile_tx(int shape) { return shape == TILE_8x8 ? 8 : (shape == TILE_32x8 ? 32 : 16); }
-int tile_ty(int shape) { return shape == TILE_8x8 ? 8 : (shape == TILE_32x8 ? 8 : 16); }
+int tile_tx(int shape)
+{
+    switch (shape) {
+    case TILE_8x8: return 8;
+    case TILE_32x8: return 32;
+    case TILE_12x12: return 12;
+    case TILE_24x8: return 24;
+    default: return 16;
+    }
+}
+int tile_ty(int shape)
+{
+    switch (shape) {
+    case TILE_8x8: case TILE_32x8: case TILE_24x8: return 8;
+    case TILE_12x12: return 12;
+    default: return 16;
+    }
+}
 
 template <typename T>
 struct Phys {
     T gamma, gm1, inv_gm1, rho_floor, p_floor;
 };
 
-constexpr int tile_threads(int tx, int ty) { return tx * ty + ((2 * (tx + ty) + 63) / 64) * 64; }
+// Threads of a tile: TX*TY interior columns, then the 2(TX+TY) ring
+// columns, rounded up to whole waves (a 12x12 tile fills exactly 3 waves).
+constexpr int tile_threads(int tx, int ty) { return ((tx * ty + 2 * (tx + ty) + 63) / 64) * 64; }
 
 template <int TX, int TY>
 struct TileGeom {
     static constexpr int NINT = TX * TY;
-    static constexpr int NRING = ((2 * (TX + TY) + 63) / 64) * 64;
-    static constexpr int NT = NINT + NRING;
+    static constexpr int NT = tile_threads(TX, TY);
 };
 
 // ------------------------------------------------------------ fast arithmetic
@@ -838,6 +855,8 @@ static int dispatch_shape_step(int shape, const PatchDesc &P, const void *u_in, 
     switch (shape) {
     case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
     case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    case TILE_12x12: return launch_step_t<T, LIM, RS, 12, 12>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    case TILE_24x8: return launch_step_t<T, LIM, RS, 24, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
     default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
     }
 }
@@ -852,6 +871,8 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
     switch (shape) {
     case TILE_8x8: return launch_batched_t<T, LIM, RS, 8, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     case TILE_32x8: return launch_batched_t<T, LIM, RS, 32, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    case TILE_12x12: return launch_batched_t<T, LIM, RS, 12, 12>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    case TILE_24x8: return launch_batched_t<T, LIM, RS, 24, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     default: return launch_batched_t<T, LIM, RS, 16, 16>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     }
 }
@@ -933,6 +954,12 @@ static int occupancy_t(int shape, int device)
         break;
     case TILE_32x8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 32, 8>, TileGeom<32, 8>::NT, 0);
+        break;
+    case TILE_12x12:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 12, 12>, TileGeom<12, 12>::NT, 0);
+        break;
+    case TILE_24x8:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 24, 8>, TileGeom<24, 8>::NT, 0);
         break;
     default:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 16, 16>, TileGeom<16, 16>::NT, 0);

@@ -80,7 +80,7 @@ def test_autotuner_picks_a_configuration_that_keeps_parity(gd):
     try:
         say("autotune step")
         choice = gd.autotune_step(ud, G, dx, dt, periodic=True)
-        assert 0 <= choice < 9
+        assert 0 <= choice < 15
         say("tuned config", gd.get_config())
         out, _ = gd.step(ud, G, dx, dt, periodic=True)
         ref, _, _ = oracle.step(u, G, dx, dt, periodic=True)
