@@ -221,18 +221,29 @@ def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     def rollout_fwd():
         return gd.rollout(u0.requires_grad_(True), GAMMA, dx, dt, nsteps, every)
 
-    uT = rollout_fwd()
+    def loss_of(uT):
+        return ((uT[0] - tgt) ** 2).sum()
+
+    # one untimed forward + backward: the first backward pays one-off costs
+    # (autograd worker start-up, first launches of torch's elementwise kernels)
+    loss_of(rollout_fwd()).backward()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    uT = rollout_fwd()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    loss = ((uT[0] - tgt) ** 2).sum()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
+    t_fwd = t_bwd = 0.0
+    reps = 3
+    for _ in range(reps):
+        u0.grad = None
+        t0 = time.perf_counter()
+        uT = rollout_fwd()
+        torch.cuda.synchronize()
+        t_fwd += time.perf_counter() - t0
+        loss = loss_of(uT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_bwd += time.perf_counter() - t0
+    t_fwd /= reps
+    t_bwd /= reps
     u0.requires_grad_(False)
     return {"workload": f"{n}^3 periodic smooth box, fixed dt, minmod + HLLC, FP64",
             "forward_step_ms": fwd, "adjoint_step_ms": adj, "adjoint_over_forward": adj / fwd,

@@ -166,7 +166,11 @@ int godunov_step_batched_cfl(gd_ctx *ctx, const gd_opts *opts, int npatch,
  * of the scheme (limiter switches, wave-speed min/max, HLLC region, floors)
  * the derivative of the branch the forward step takes is used. Every
  * element of lam_in is written exactly once (gather form, deterministic).
- * GD_F64 only; lam_in must not overlap any input. */
+ * GD_F64 only (GD_E_UNSUPPORTED otherwise); lam_in must not overlap any
+ * input (GD_E_ARG). The library keeps a device scratch of about 320 bytes
+ * per cell of the box extended by two layers, (nx+4)(ny+4)(nz+4), grown on
+ * first use (the growth synchronises the device; GD_E_NOMEM if it fails);
+ * boxes with 15 (nx+4)(ny+4)(nz+4) >= 2^31 return GD_E_UNSUPPORTED. */
 int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
                          const void *u_in, const void *lam_out, const void *lam_bflux,
                          void *lam_in, double gamma, double dx, double dt, void *hip_stream);

@@ -516,12 +516,14 @@ int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int n
     if (overlap(lam_in, nin, u_in, nin) || overlap(lam_in, nin, lam_out, nout) ||
         (lam_bflux && overlap(lam_in, nin, lam_bflux, nfl)))
         return fail(ctx, GD_E_ARG, "lam_in overlaps an input");
-    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
-    if ((r = set_device(ctx))) return r;
     gd::PatchDesc P{};
     P.nx = nx; P.ny = ny; P.nz = nz; P.ng = periodic ? 0 : ng; P.periodic = periodic;
     P.flux_off = lam_bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
+    if (!gd::adjoint_fits_32bit(P))
+        return fail(ctx, GD_E_UNSUPPORTED, "the adjoint supports boxes of up to 2^31/15 extended cells");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t need = gd::adjoint_scratch_bytes(P);
     if (need > ctx->adj_bytes) {

@@ -79,6 +79,9 @@ int launch_cfl_single(int dtype, const PatchDesc &P, const void *u, const Scalar
 // Bytes of device scratch the adjoint of one patch needs.
 size_t adjoint_scratch_bytes(const PatchDesc &P);
 
+// Whether the adjoint's 32-bit indexing covers the patch.
+bool adjoint_fits_32bit(const PatchDesc &P);
+
 int launch_adjoint(int limiter, int riemann, const PatchDesc &P, const double *u_in,
                    const double *lam_out, const double *lam_bflux, double *lam_in,
                    const Scalars &sc, double dt, double *scratch, hipStream_t s);

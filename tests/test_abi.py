@@ -100,6 +100,17 @@ def test_adjoint_rejects_fp32(lib):
     assert r == -4
 
 
+@pytest.mark.parametrize("n,expect", [(600, -4), (500, -1)])
+def test_adjoint_rejects_boxes_beyond_32bit_indexing(lib, n, expect):
+    """15 (n+4)^3 scratch entries must stay below 2^31: 600^3 is refused on
+    the host; 500^3 passes that check and stops at the NULL context."""
+    o = _opts(bc=1)
+    r = lib.godunov_step_adjoint(None, ctypes.byref(o), n, n, n, 0, ctypes.c_void_p(1 << 40),
+                                 ctypes.c_void_p(2 << 40), None, ctypes.c_void_p(3 << 40),
+                                 5 / 3, 0.1, 0.01, None)
+    assert r == expect
+
+
 def test_create_without_device_fails_cleanly(lib):
     import torch
     if torch.cuda.is_available():
