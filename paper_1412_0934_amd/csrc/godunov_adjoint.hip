@@ -329,8 +329,10 @@ __device__ __forceinline__ void hllc_adjoint(double g, double inv_gm1, const dou
     else if (f.SR > 0.0) left = false;
     else { flux_cons_adjoint(inv_gm1, R, Fb, zero, Rb); return; }
 
-    const double *K = left ? L : R;
-    double *Kb = left ? Lb : Rb;
+    // the star state on the side of the contact the face lies on; values
+    // are selected (not pointers), so that everything stays in registers
+    double K[5], Kb[5] = { 0, 0, 0, 0, 0 };
+    for (int q = 0; q < 5; ++q) K[q] = left ? L[q] : R[q];
     const double SK = left ? f.SL : f.SR, mK = left ? mL : mR;
     const double iK0 = left ? f.iL0 : f.iR0;
     double FK[5], UK[5];
@@ -368,6 +370,10 @@ __device__ __forceinline__ void hllc_adjoint(double g, double inv_gm1, const dou
     SKb += db;
     Sstb -= db;
     flux_cons_adjoint(inv_gm1, K, Fb, UKb, Kb);
+    for (int q = 0; q < 5; ++q) {
+        Lb[q] += left ? Kb[q] : 0.0;
+        Rb[q] += left ? 0.0 : Kb[q];
+    }
 
     double SLb = 0.0, SRb = 0.0, mLb = 0.0, mRb = 0.0;
     if (left) { SLb += SKb; mLb += mKb; } else { SRb += SKb; mRb += mKb; }
@@ -414,23 +420,18 @@ __device__ __forceinline__ void hll_adjoint(double g, double inv_gm1, const doub
     speeds_adjoint(f, SLb, SRb, Lb, Rb);
 }
 
-// Adjoint of the two face states of the face along D whose right cell is
-// (i, j, k) and left cell (i, j, k) - e_D: dL/dF reversed through the
-// Riemann solver and the face-state floors, in unrotated variables.
+// Adjoint of the two face states WL, WR (before the floors) of the face
+// along D whose right cell is (i, j, k) and left cell (i, j, k) - e_D: dL/dF
+// reversed through the Riemann solver and the face-state floors, in
+// unrotated variables.
 template <int RS, int D>
-__device__ __forceinline__ void face_adjoint(const Geo &g, const Scratch &s, int i, int j, int k,
-                                             const double *__restrict__ lam_out,
+__device__ __forceinline__ void face_adjoint(const Geo &g, int i, int j, int k, double WL[5],
+                                             double WR[5], const double *__restrict__ lam_out,
                                              const double *__restrict__ lam_bflux, double WLb[5],
                                              double WRb[5])
 {
     const int li = i - (D == 0), lj = j - (D == 1), lk = k - (D == 2);
-    const int el = ext(g, li, lj, lk), er = ext(g, i, j, k);
     constexpr int nt1 = 1 + (D + 1) % 3, nt2 = 1 + (D + 2) % 3, nn = 1 + D;
-    double WL[5], WR[5];
-    for (int q = 0; q < 5; ++q) {
-        WL[q] = s.fw[rec(el, F_WS + q)] + 0.5 * s.fw[rec(el, F_S + D * 5 + q)];
-        WR[q] = s.fw[rec(er, F_WS + q)] - 0.5 * s.fw[rec(er, F_S + D * 5 + q)];
-    }
     const bool flL0 = WL[0] < g.rho_floor, flL4 = WL[4] < g.p_floor;
     const bool flR0 = WR[0] < g.rho_floor, flR4 = WR[4] < g.p_floor;
     if (flL0) WL[0] = g.rho_floor;
@@ -442,8 +443,8 @@ __device__ __forceinline__ void face_adjoint(const Geo &g, const Scratch &s, int
     // (in a periodic box both cells are interior cells, wrapped)
     const bool right_in = g.periodic || (i < g.nx && j < g.ny && k < g.nz);
     const bool left_in = g.periodic || (li >= 0 && lj >= 0 && lk >= 0);
-    const int ir = g.periodic ? er : (right_in ? interior_index(g, i, j, k) : 0);
-    const int il = g.periodic ? el : (left_in ? interior_index(g, li, lj, lk) : 0);
+    const int ir = g.periodic ? ext(g, i, j, k) : (right_in ? interior_index(g, i, j, k) : 0);
+    const int il = g.periodic ? ext(g, li, lj, lk) : (left_in ? interior_index(g, li, lj, lk) : 0);
     double Fb[5];
     for (int q = 0; q < 5; ++q) {
         double v = 0.0;
@@ -482,11 +483,18 @@ __device__ __forceinline__ void face_adjoint(const Geo &g, const Scratch &s, int
 
 // ------------------------------------------------------------ 2: cells
 
-// LDS of the cells kernel: the two face-state adjoints ([side][q][slot],
-// side 0 the left state) of the x and y faces of one plane of the tile.
+// LDS of the cells kernel, for the x faces of one plane of the tile (and
+// likewise for y): per cell of the row range [-1, CTX] (the tile and one
+// halo cell on each side), plus[q] = W* + S_x/2, the left state of its upper
+// face, and minus[q] = W* - S_x/2, the right state of its lower face. Each
+// face task reads the plus state of its left cell and the minus state of
+// its right cell and overwrites both with their adjoints; no other task
+// touches them, so afterwards a cell finds the adjoints of its own two face
+// states in its own slots.
+constexpr int XW = CTX + 2, YW = CTY + 2;
 struct CellsSmem {
-    double x[2][5][NXF];
-    double y[2][5][NYF];
+    double xp[5][CTY][XW], xm[5][CTY][XW];
+    double yp[5][YW][CTX], ym[5][YW][CTX];
 };
 
 // A face along D exists when its index along D lies in [0, n_D] and the
@@ -501,22 +509,61 @@ __device__ __forceinline__ bool face_exists(const Geo &g, int i, int j, int k)
     return ok;
 }
 
-// The x (D = 0) or y (D = 1) faces of plane k of the tile: slot (sx, sy)
-// holds the face whose right cell is (i0 + sx, j0 + sy, k).
+// whether cell (i, j, k) has a slot in the scratch records
+__device__ __forceinline__ bool in_scratch(const Geo &g, int i, int j, int k)
+{
+    return g.periodic || (i >= -2 && i < g.nx + 2 && j >= -2 && j < g.ny + 2 && k >= -2 &&
+                          k < g.nz + 2);
+}
+
+// W* +- S_D/2 of cell (i, j, k) (zero outside the scratch box)
+template <int D>
+__device__ __forceinline__ void face_states(const Geo &g, const Scratch &s, int i, int j, int k,
+                                            double P[5], double M[5])
+{
+    if (!in_scratch(g, i, j, k)) {
+        for (int q = 0; q < 5; ++q) { P[q] = 0.0; M[q] = 0.0; }
+        return;
+    }
+    const int e = ext(g, i, j, k);
+    for (int q = 0; q < 5; ++q) {
+        const double w = s.fw[rec(e, F_WS + q)], h = 0.5 * s.fw[rec(e, F_S + D * 5 + q)];
+        P[q] = w + h;
+        M[q] = w - h;
+    }
+}
+
+// The x (D = 0) or y (D = 1) face tasks of a plane, on the staged states.
 template <int RS, int D>
-__device__ __forceinline__ void plane_faces(const Geo &g, const Scratch &s, int i0, int j0, int k,
+__device__ __forceinline__ void plane_faces(const Geo &g, int i0, int j0, int k,
                                             const double *__restrict__ lam_out,
-                                            const double *__restrict__ lam_bflux,
-                                            double (*f)[5][D == 0 ? NXF : NYF])
+                                            const double *__restrict__ lam_bflux, CellsSmem &sm)
 {
     constexpr int SX = CTX + (D == 0), NS = D == 0 ? NXF : NYF;
-    for (int t = threadIdx.x; t < NS; t += CT) {
-        const int i = i0 + t % SX, j = j0 + t / SX;
-        double WLb[5] = { 0, 0, 0, 0, 0 }, WRb[5] = { 0, 0, 0, 0, 0 };
-        if (face_exists<D>(g, i, j, k)) face_adjoint<RS, D>(g, s, i, j, k, lam_out, lam_bflux, WLb, WRb);
+    // NS exceeds the thread count by a few tasks; the y pass hands its extra
+    // tasks to the second wave, so that no wave does two extra rounds
+    const int first = D == 0 ? threadIdx.x : (threadIdx.x + CT - 64) % CT;
+    for (int t = first; t < NS; t += CT) {
+        // slot (sx, sy): the face whose right cell is (i0 + sx, j0 + sy, k)
+        const int sx = t % SX, sy = t / SX;
+        const int i = i0 + sx, j = j0 + sy;
+        if (!face_exists<D>(g, i, j, k)) {
+            for (int q = 0; q < 5; ++q) {
+                if (D == 0) { sm.xp[q][sy][sx] = 0.0; sm.xm[q][sy][sx + 1] = 0.0; }
+                else { sm.yp[q][sy][sx] = 0.0; sm.ym[q][sy + 1][sx] = 0.0; }
+            }
+            continue;
+        }
+        // the left cell sits at x index sx - 1 of the staged row, i.e. slot sx
+        double WL[5], WR[5], WLb[5], WRb[5];
         for (int q = 0; q < 5; ++q) {
-            f[0][q][t] = WLb[q];
-            f[1][q][t] = WRb[q];
+            WL[q] = D == 0 ? sm.xp[q][sy][sx] : sm.yp[q][sy][sx];
+            WR[q] = D == 0 ? sm.xm[q][sy][sx + 1] : sm.ym[q][sy + 1][sx];
+        }
+        face_adjoint<RS, D>(g, i, j, k, WL, WR, lam_out, lam_bflux, WLb, WRb);
+        for (int q = 0; q < 5; ++q) {
+            if (D == 0) { sm.xp[q][sy][sx] = WLb[q]; sm.xm[q][sy][sx + 1] = WRb[q]; }
+            else { sm.yp[q][sy][sx] = WLb[q]; sm.ym[q][sy + 1][sx] = WRb[q]; }
         }
     }
 }
@@ -542,37 +589,70 @@ __global__ __launch_bounds__(CT) void k_cells(Geo g, const double *__restrict__ 
 
     // right-state adjoint of the z face below the first plane
     double zlo[5] = { 0, 0, 0, 0, 0 };
-    {
-        double t[5] = { 0, 0, 0, 0, 0 };
-        if (face_exists<2>(g, i, j, kb)) face_adjoint<RS, 2>(g, s, i, j, kb, lam_out, lam_bflux, t, zlo);
+    if (face_exists<2>(g, i, j, kb)) {
+        double P[5], M[5], WL[5], WR[5], t[5];
+        face_states<2>(g, s, i, j, kb - 1, WL, M);
+        face_states<2>(g, s, i, j, kb, P, WR);
+        face_adjoint<RS, 2>(g, i, j, kb, WL, WR, lam_out, lam_bflux, t, zlo);
     }
     for (int k = kb; k < ke; ++k) {
-        plane_faces<RS, 0>(g, s, i0, j0, k, lam_out, lam_bflux, sm.x);
-        plane_faces<RS, 1>(g, s, i0, j0, k, lam_out, lam_bflux, sm.y);
+        // stage the x and y face states of the plane: every thread its own
+        // cell, the first wave the 64 halo cells
+        {
+            double P[5], M[5];
+            face_states<0>(g, s, i, j, k, P, M);
+            for (int q = 0; q < 5; ++q) { sm.xp[q][ty][tx + 1] = P[q]; sm.xm[q][ty][tx + 1] = M[q]; }
+            face_states<1>(g, s, i, j, k, P, M);
+            for (int q = 0; q < 5; ++q) { sm.yp[q][ty + 1][tx] = P[q]; sm.ym[q][ty + 1][tx] = M[q]; }
+            if (threadIdx.x < 2 * (CTX + CTY)) {
+                const int h = threadIdx.x;
+                if (h < 2 * CTY) {
+                    // x halo: column -1 (plus state) or column CTX (minus state)
+                    const int r = h % CTY, right = h / CTY;
+                    const int hx = right ? CTX : -1;
+                    face_states<0>(g, s, i0 + hx, j0 + r, k, P, M);
+                    for (int q = 0; q < 5; ++q) {
+                        if (right) sm.xm[q][r][CTX + 1] = M[q];
+                        else sm.xp[q][r][0] = P[q];
+                    }
+                } else {
+                    const int c = (h - 2 * CTY) % CTX, top = (h - 2 * CTY) / CTX;
+                    const int hy = top ? CTY : -1;
+                    face_states<1>(g, s, i0 + c, j0 + hy, k, P, M);
+                    for (int q = 0; q < 5; ++q) {
+                        if (top) sm.ym[q][CTY + 1][c] = M[q];
+                        else sm.yp[q][0][c] = P[q];
+                    }
+                }
+            }
+        }
+        // the z face above the cell, in registers
         double zl[5] = { 0, 0, 0, 0, 0 }, zr[5] = { 0, 0, 0, 0, 0 };
-        if (face_exists<2>(g, i, j, k + 1)) face_adjoint<RS, 2>(g, s, i, j, k + 1, lam_out, lam_bflux, zl, zr);
+        if (face_exists<2>(g, i, j, k + 1)) {
+            double P[5], M[5], WL[5], WR[5];
+            face_states<2>(g, s, i, j, k, WL, M);
+            face_states<2>(g, s, i, j, k + 1, P, WR);
+            face_adjoint<RS, 2>(g, i, j, k + 1, WL, WR, lam_out, lam_bflux, zl, zr);
+        }
+        __syncthreads();
+        plane_faces<RS, 0>(g, i0, j0, k, lam_out, lam_bflux, sm);
+        plane_faces<RS, 1>(g, i0, j0, k, lam_out, lam_bflux, sm);
         __syncthreads();
 
         // the adjoints of the cell's face states: the left state of its upper
         // face is W* + S/2, the right state of its lower face is W* - S/2
         double Wsb[5] = { 0, 0, 0, 0, 0 }, Sb[3][5];
-        {
-            const int up = ty * (CTX + 1) + tx + 1, dn = ty * (CTX + 1) + tx;
-            for (int q = 0; q < 5; ++q) {
-                const double vl = sm.x[0][q][up], vr = sm.x[1][q][dn];
-                Wsb[q] += vl;
-                Wsb[q] += vr;
-                Sb[0][q] = 0.5 * vl - 0.5 * vr;
-            }
+        for (int q = 0; q < 5; ++q) {
+            const double vl = sm.xp[q][ty][tx + 1], vr = sm.xm[q][ty][tx + 1];
+            Wsb[q] += vl;
+            Wsb[q] += vr;
+            Sb[0][q] = 0.5 * vl - 0.5 * vr;
         }
-        {
-            const int up = (ty + 1) * CTX + tx, dn = ty * CTX + tx;
-            for (int q = 0; q < 5; ++q) {
-                const double vl = sm.y[0][q][up], vr = sm.y[1][q][dn];
-                Wsb[q] += vl;
-                Wsb[q] += vr;
-                Sb[1][q] = 0.5 * vl - 0.5 * vr;
-            }
+        for (int q = 0; q < 5; ++q) {
+            const double vl = sm.yp[q][ty + 1][tx], vr = sm.ym[q][ty + 1][tx];
+            Wsb[q] += vl;
+            Wsb[q] += vr;
+            Sb[1][q] = 0.5 * vl - 0.5 * vr;
         }
         for (int q = 0; q < 5; ++q) {
             Wsb[q] += zl[q];
