@@ -420,17 +420,27 @@ __device__ __forceinline__ void hll_adjoint(double g, double inv_gm1, const doub
     speeds_adjoint(f, SLb, SRb, Lb, Rb);
 }
 
+// dL/dU' of cell (i, j, k), zero for cells outside the patch interior
+// (which have no update)
+__device__ __forceinline__ void lam_at(const Geo &g, const double *__restrict__ lam_out, int i,
+                                       int j, int k, double L[5])
+{
+    const bool in = g.periodic || (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz);
+    const int c = g.periodic ? ext(g, i, j, k) : (in ? interior_index(g, i, j, k) : 0);
+    for (int q = 0; q < 5; ++q) L[q] = in ? lam_out[q * g.nint + c] : 0.0;
+}
+
 // Adjoint of the two face states WL, WR (before the floors) of the face
-// along D whose right cell is (i, j, k) and left cell (i, j, k) - e_D: dL/dF
-// reversed through the Riemann solver and the face-state floors, in
-// unrotated variables.
+// along D whose right cell is (i, j, k) and left cell (i, j, k) - e_D, whose
+// updates have adjoints lamL and lamR: dL/dF reversed through the Riemann
+// solver and the face-state floors, in unrotated variables.
 template <int RS, int D>
 __device__ __forceinline__ void face_adjoint(const Geo &g, int i, int j, int k, double WL[5],
-                                             double WR[5], const double *__restrict__ lam_out,
+                                             double WR[5], const double lamL[5],
+                                             const double lamR[5],
                                              const double *__restrict__ lam_bflux, double WLb[5],
                                              double WRb[5])
 {
-    const int li = i - (D == 0), lj = j - (D == 1), lk = k - (D == 2);
     constexpr int nt1 = 1 + (D + 1) % 3, nt2 = 1 + (D + 2) % 3, nn = 1 + D;
     const bool flL0 = WL[0] < g.rho_floor, flL4 = WL[4] < g.p_floor;
     const bool flR0 = WR[0] < g.rho_floor, flR4 = WR[4] < g.p_floor;
@@ -440,18 +450,8 @@ __device__ __forceinline__ void face_adjoint(const Geo &g, int i, int j, int k, 
     if (flR4) WR[4] = g.p_floor;
 
     // dL/dF: the right cell's update has -c F(face), the left cell's +c F
-    // (in a periodic box both cells are interior cells, wrapped)
-    const bool right_in = g.periodic || (i < g.nx && j < g.ny && k < g.nz);
-    const bool left_in = g.periodic || (li >= 0 && lj >= 0 && lk >= 0);
-    const int ir = g.periodic ? ext(g, i, j, k) : (right_in ? interior_index(g, i, j, k) : 0);
-    const int il = g.periodic ? ext(g, li, lj, lk) : (left_in ? interior_index(g, li, lj, lk) : 0);
     double Fb[5];
-    for (int q = 0; q < 5; ++q) {
-        double v = 0.0;
-        if (right_in) v += g.c * lam_out[q * g.nint + ir];
-        if (left_in) v -= g.c * lam_out[q * g.nint + il];
-        Fb[q] = v;
-    }
+    for (int q = 0; q < 5; ++q) Fb[q] = g.c * lamR[q] - g.c * lamL[q];
     const int n_d = D == 0 ? g.nx : (D == 1 ? g.ny : g.nz);
     const int fi = D == 0 ? i : (D == 1 ? j : k);
     if (lam_bflux && (fi == 0 || fi == n_d)) {
@@ -491,10 +491,13 @@ __device__ __forceinline__ void face_adjoint(const Geo &g, int i, int j, int k, 
 // its right cell and overwrites both with their adjoints; no other task
 // touches them, so afterwards a cell finds the adjoints of its own two face
 // states in its own slots.
+// lam holds dL/dU' of the tile and its one-deep x and y halo, at tile
+// coordinates + 1.
 constexpr int XW = CTX + 2, YW = CTY + 2;
 struct CellsSmem {
     double xp[5][CTY][XW], xm[5][CTY][XW];
     double yp[5][YW][CTX], ym[5][YW][CTX];
+    double lam[5][YW][XW];
 };
 
 // A face along D exists when its index along D lies in [0, n_D] and the
@@ -536,7 +539,6 @@ __device__ __forceinline__ void face_states(const Geo &g, const Scratch &s, int 
 // The x (D = 0) or y (D = 1) face tasks of a plane, on the staged states.
 template <int RS, int D>
 __device__ __forceinline__ void plane_faces(const Geo &g, int i0, int j0, int k,
-                                            const double *__restrict__ lam_out,
                                             const double *__restrict__ lam_bflux, CellsSmem &sm)
 {
     constexpr int SX = CTX + (D == 0), NS = D == 0 ? NXF : NYF;
@@ -555,12 +557,14 @@ __device__ __forceinline__ void plane_faces(const Geo &g, int i0, int j0, int k,
             continue;
         }
         // the left cell sits at x index sx - 1 of the staged row, i.e. slot sx
-        double WL[5], WR[5], WLb[5], WRb[5];
+        double WL[5], WR[5], WLb[5], WRb[5], lamL[5], lamR[5];
         for (int q = 0; q < 5; ++q) {
             WL[q] = D == 0 ? sm.xp[q][sy][sx] : sm.yp[q][sy][sx];
             WR[q] = D == 0 ? sm.xm[q][sy][sx + 1] : sm.ym[q][sy + 1][sx];
+            lamL[q] = D == 0 ? sm.lam[q][sy + 1][sx] : sm.lam[q][sy][sx + 1];
+            lamR[q] = sm.lam[q][sy + 1][sx + 1];
         }
-        face_adjoint<RS, D>(g, i, j, k, WL, WR, lam_out, lam_bflux, WLb, WRb);
+        face_adjoint<RS, D>(g, i, j, k, WL, WR, lamL, lamR, lam_bflux, WLb, WRb);
         for (int q = 0; q < 5; ++q) {
             if (D == 0) { sm.xp[q][sy][sx] = WLb[q]; sm.xm[q][sy][sx + 1] = WRb[q]; }
             else { sm.yp[q][sy][sx] = WLb[q]; sm.ym[q][sy + 1][sx] = WRb[q]; }
@@ -587,13 +591,17 @@ __global__ __launch_bounds__(CT) void k_cells(Geo g, const double *__restrict__ 
     const int i = i0 + tx, j = j0 + ty;
     const bool col = i < g.lo + g.px && j < g.lo + g.py;
 
+    // dL/dU' of the column's cell in the current plane, carried up the march
+    double lamk[5];
+    lam_at(g, lam_out, i, j, kb, lamk);
     // right-state adjoint of the z face below the first plane
     double zlo[5] = { 0, 0, 0, 0, 0 };
     if (face_exists<2>(g, i, j, kb)) {
-        double P[5], M[5], WL[5], WR[5], t[5];
+        double P[5], M[5], WL[5], WR[5], t[5], lamb[5];
         face_states<2>(g, s, i, j, kb - 1, WL, M);
         face_states<2>(g, s, i, j, kb, P, WR);
-        face_adjoint<RS, 2>(g, i, j, kb, WL, WR, lam_out, lam_bflux, t, zlo);
+        lam_at(g, lam_out, i, j, kb - 1, lamb);
+        face_adjoint<RS, 2>(g, i, j, kb, WL, WR, lamb, lamk, lam_bflux, t, zlo);
     }
     for (int k = kb; k < ke; ++k) {
         // stage the x and y face states of the plane: every thread its own
@@ -604,39 +612,48 @@ __global__ __launch_bounds__(CT) void k_cells(Geo g, const double *__restrict__ 
             for (int q = 0; q < 5; ++q) { sm.xp[q][ty][tx + 1] = P[q]; sm.xm[q][ty][tx + 1] = M[q]; }
             face_states<1>(g, s, i, j, k, P, M);
             for (int q = 0; q < 5; ++q) { sm.yp[q][ty + 1][tx] = P[q]; sm.ym[q][ty + 1][tx] = M[q]; }
+            for (int q = 0; q < 5; ++q) sm.lam[q][ty + 1][tx + 1] = lamk[q];
             if (threadIdx.x < 2 * (CTX + CTY)) {
                 const int h = threadIdx.x;
+                double L[5];
                 if (h < 2 * CTY) {
                     // x halo: column -1 (plus state) or column CTX (minus state)
                     const int r = h % CTY, right = h / CTY;
                     const int hx = right ? CTX : -1;
                     face_states<0>(g, s, i0 + hx, j0 + r, k, P, M);
+                    lam_at(g, lam_out, i0 + hx, j0 + r, k, L);
                     for (int q = 0; q < 5; ++q) {
                         if (right) sm.xm[q][r][CTX + 1] = M[q];
                         else sm.xp[q][r][0] = P[q];
+                        sm.lam[q][r + 1][hx + 1] = L[q];
                     }
                 } else {
+                    // y halo: row -1 (plus state) or row CTY (minus state)
                     const int c = (h - 2 * CTY) % CTX, top = (h - 2 * CTY) / CTX;
                     const int hy = top ? CTY : -1;
                     face_states<1>(g, s, i0 + c, j0 + hy, k, P, M);
+                    lam_at(g, lam_out, i0 + c, j0 + hy, k, L);
                     for (int q = 0; q < 5; ++q) {
                         if (top) sm.ym[q][CTY + 1][c] = M[q];
                         else sm.yp[q][0][c] = P[q];
+                        sm.lam[q][hy + 1][c + 1] = L[q];
                     }
                 }
             }
         }
         // the z face above the cell, in registers
-        double zl[5] = { 0, 0, 0, 0, 0 }, zr[5] = { 0, 0, 0, 0, 0 };
+        double zl[5] = { 0, 0, 0, 0, 0 }, zr[5] = { 0, 0, 0, 0, 0 }, lamk1[5];
+        lam_at(g, lam_out, i, j, k + 1, lamk1);
         if (face_exists<2>(g, i, j, k + 1)) {
             double P[5], M[5], WL[5], WR[5];
             face_states<2>(g, s, i, j, k, WL, M);
             face_states<2>(g, s, i, j, k + 1, P, WR);
-            face_adjoint<RS, 2>(g, i, j, k + 1, WL, WR, lam_out, lam_bflux, zl, zr);
+            face_adjoint<RS, 2>(g, i, j, k + 1, WL, WR, lamk, lamk1, lam_bflux, zl, zr);
         }
+        for (int q = 0; q < 5; ++q) lamk[q] = lamk1[q];
         __syncthreads();
-        plane_faces<RS, 0>(g, i0, j0, k, lam_out, lam_bflux, sm);
-        plane_faces<RS, 1>(g, i0, j0, k, lam_out, lam_bflux, sm);
+        plane_faces<RS, 0>(g, i0, j0, k, lam_bflux, sm);
+        plane_faces<RS, 1>(g, i0, j0, k, lam_bflux, sm);
         __syncthreads();
 
         // the adjoints of the cell's face states: the left state of its upper
