@@ -40,34 +40,45 @@ if ROOT not in sys.path:
 GAMMA = 5.0 / 3.0
 HBM_PEAK_GBS = 8000.0
 METRIC = "Mcell-updates/s per Godunov step (plain vs batched), % HBM roofline; adjoint/fwd"
-KERNEL_SRC = os.path.join(ROOT, "paper_1412_0934_amd", "csrc", "godunov_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1412_0934_amd", "csrc", f)
+              for f in ("godunov_kernels.hip", "godunov_math.h", "godunov_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_traffic.txt")
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(tile_config=None):
+def measured_traffic(tile_config):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary, if it was taken on the current kernel source and the same tile
-    configuration; else None."""
+    summary, if it was taken on the current kernel source and holds a
+    measurement for this tile configuration; else None. The summary has one
+    block of "key: value" lines per configuration, each opened by its
+    tile_config line."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    vals = {}
+    blocks, cur = [], None
     for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    if tile_config is not None and vals.get("tile_config") != tile_config:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        if ":" not in line or line.startswith("#"):
+            continue
+        k, v = (x.strip() for x in line.split(":", 1))
+        if k == "tile_config":
+            cur = {}
+            blocks.append(cur)
+        if cur is not None:
+            cur[k] = v
+    for b in blocks:
+        if (b.get("tile_config") == tile_config and
+                b.get("kernel_source_sha256_16") == kernel_source_hash()):
+            try:
+                return float(b["hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def log(*a):
@@ -214,6 +225,10 @@ def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / k
 
+    # the forward step it is compared with runs in the configuration the
+    # autotuner picks for this box
+    gd.autotune_step(u0, GAMMA, dx, dt, periodic=True, out=out)
+    fwd_cfg = gd.get_config(torch.float64)
     fwd = timed(lambda: gd.step(u0, GAMMA, dx, dt, periodic=True, want_bflux=False, out=out), steps)
     adj = timed(lambda: gd.step_adjoint(u0, lam, GAMMA, dx, dt, periodic=True, out=lin), steps)
     tgt = torch.from_numpy(target).cuda()
@@ -246,7 +261,9 @@ def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     t_bwd /= reps
     u0.requires_grad_(False)
     return {"workload": f"{n}^3 periodic smooth box, fixed dt, minmod + HLLC, FP64",
-            "forward_step_ms": fwd, "adjoint_step_ms": adj, "adjoint_over_forward": adj / fwd,
+            "forward_step_ms": fwd, "forward_config": f"{fwd_cfg['shape_single']}/"
+                                                      f"{fwd_cfg['zlen_single']}",
+            "adjoint_step_ms": adj, "adjoint_over_forward": adj / fwd,
             "rollout": f"{nsteps} steps, checkpoint every {every}",
             "rollout_forward_ms": 1e3 * t_fwd, "rollout_backward_ms": 1e3 * t_bwd,
             "rollout_backward_over_forward": t_bwd / t_fwd}
