@@ -269,6 +269,45 @@ def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
             "rollout_backward_over_forward": t_bwd / t_fwd}
 
 
+# Ramses hydro solver in one cosmological AMR run (256^3 base mesh, 8 levels),
+# whole-run seconds as printed in Sec. 3 (Table 1); the paper gives neither the
+# cell count nor the step count, so none converts to Mcell-updates/s.
+PAPER_CONTEXT = {
+    "source": "Sec. 3, Table 1: Ramses hydro solver (OpenACC) in a cosmological AMR run, "
+              "256^3 base mesh + 8 levels, Piz Daint (Cray XC30)",
+    "hydro_seconds": {"1 CPU core (Xeon E5-2670)": 56218, "16 CPU cores": 2918,
+                      "1 GPU (Tesla K20X)": 3009, "16 GPUs (K20X)": 179},
+    "gpu_copy_seconds": {"1 GPU": 739, "16 GPUs": 64},
+    "note": "context, not a target: no cell or step counts are given, so no Mcell-updates/s",
+}
+
+
+def cpu_single_thread(u0):
+    """One full step (cfl + step) of the oracle on one host thread, in a child
+    process started with OMP_NUM_THREADS=1."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "u0.npy")
+        np.save(path, u0)
+        code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+                "u = np.load(%r); n = u.shape[1]; t0 = time.perf_counter(); "
+                "dt = oracle.cfl_dt(u, %r, 1.0 / n, 0.5, periodic=True); "
+                "oracle.step(u, %r, 1.0 / n, dt, periodic=True); "
+                "print(time.perf_counter() - t0)" % (ROOT, path, GAMMA, GAMMA))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        log("bench: CPU oracle on 1 thread")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                           text=True, timeout=300)
+    if r.returncode != 0:
+        return None
+    el = float(r.stdout.strip().splitlines()[-1])
+    n = u0.shape[1]
+    return {"value": round(n ** 3 / el / 1e6, 3), "unit": "Mcell-updates/s", "cores": 1,
+            "sample": f"1 full step (cfl + step) of the same {n}^3 box, {el:.1f} s"}
+
+
 def cpu_baseline(u0, budget_s=12.0, max_steps=40):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -370,6 +409,10 @@ def main():
         line["also"] = also
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["u0"])
+        single = cpu_single_thread(r["u0"])
+        if single is not None:
+            line["cpu_baseline"]["single_thread"] = single
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
 
