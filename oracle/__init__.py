@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package. The GPU library never
 loads it, and it shares no code with the GPU path: the C sources here are
-compiled by gcc into ``liboracle.so`` (double) and ``liboracle_cs.so``
-(double complex, a complex-step tangent-linear model of the same forward code).
+compiled by gcc into ``liboracle.so`` (double), ``liboracle_cs.so``
+(double complex, a complex-step tangent-linear model of the same forward code)
+and ``libmhd_oracle.so`` (the ideal-MHD step, wrapped by ``oracle.mhd``).
 
 The step follows the paper's method family (Sec. 2: Euler equations of an
 ideal gas, piecewise-linear Godunov scheme; Sec. 3: ghost-zoned patches;
@@ -41,6 +42,9 @@ def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE) -> 
         common + ["-DORACLE_COMPLEX_STEP", "-o", os.path.join(out_dir, "liboracle_cs.so"),
                   os.path.join(src_dir, "godunov_oracle.c"), "-lm"],
     ]
+    mhd_src = os.path.join(src_dir, "mhd_oracle.c")
+    if os.path.exists(mhd_src):
+        cmds.append(common + ["-o", os.path.join(out_dir, "libmhd_oracle.so"), mhd_src, "-lm"])
     for cmd in cmds:
         if verbose:
             print(" ".join(cmd))

@@ -304,3 +304,83 @@ def smooth_box(n=128, gamma=GAMMA, amplitude=0.05, seeds=(13, 14, 15, 16, 17, 18
     vel = [amplitude * cs * _mode_sum(n, np.random.default_rng(s)) for s in seeds[2:5]]
     target = 1.0 + amplitude * _mode_sum(n, np.random.default_rng(seeds[5]))
     return conserved(rho, vel[0], vel[1], vel[2], p, gamma), target
+
+
+# ------------------------------------------------------------ ideal MHD
+
+def mhd_conserved(rho, vx, vy, vz, p, bx, by, bz, psi=None, gamma=GAMMA):
+    """(9, ...) conserved MHD state (rho, rho v, E, B, psi) from primitives,
+    E = p/(gamma-1) + rho |v|^2/2 + |B|^2/2 (units with mu0 = 1)."""
+    rho, vx, vy, vz, p, bx, by, bz = np.broadcast_arrays(rho, vx, vy, vz, p, bx, by, bz)
+    out = np.empty((9,) + rho.shape)
+    out[0] = rho
+    out[1] = rho * vx
+    out[2] = rho * vy
+    out[3] = rho * vz
+    out[4] = (p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+              + 0.5 * (bx * bx + by * by + bz * bz))
+    out[5], out[6], out[7] = bx, by, bz
+    out[8] = 0.0 if psi is None else psi
+    return out
+
+
+def alfven_wave(n, amplitude=0.1, gamma=GAMMA, axis=0):
+    """Circularly polarised Alfven wave along `axis` on a periodic n-cell line
+    (the other extents 1): rho = 1, p = 0.1, B_par = 1, B_perp of constant
+    magnitude `amplitude` rotating with phase 2 pi x, v_perp = -B_perp / sqrt(rho)
+    (a wave moving in +x at v_A = 1; an exact nonlinear solution, period 1)."""
+    x = (np.arange(n) + 0.5) / n
+    b1, b2 = amplitude * np.sin(2 * np.pi * x), amplitude * np.cos(2 * np.pi * x)
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    t1, t2 = (axis + 1) % 3, (axis + 2) % 3
+    vel, B = [None] * 3, [None] * 3
+    vel[axis], B[axis] = np.zeros(n), np.ones(n)
+    vel[t1], vel[t2], B[t1], B[t2] = -b1, -b2, b1, b2
+    one = np.ones(n)
+    U = mhd_conserved(one, vel[0], vel[1], vel[2], 0.1 * one, B[0], B[1], B[2], gamma=gamma)
+    return U.reshape((9,) + tuple(shape))
+
+
+def mhd_turbulent_box(n=128, gamma=GAMMA, mach=1.0, beta=100.0, sigma_ln=1.0,
+                      seeds=(1, 2, 3, 4, 5, 6, 7)):
+    """Periodic (9, n, n, n) MHD state: density and velocities as in
+    turbulent_box at rms Mach `mach`; B from three independent k^-11/3
+    Gaussian random fields (not projected, so div B is not zero), scaled so
+    that the mean plasma beta 2<p>/<|B|^2> equals `beta`; psi = 0."""
+    s = gaussian_random_field(n, seeds[0])
+    rho = np.exp(sigma_ln * s - 0.5 * sigma_ln ** 2)
+    vel = [gaussian_random_field(n, sd) for sd in seeds[1:4]]
+    vel = [v - v.mean() for v in vel]
+    rms = math.sqrt(float(np.mean(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)))
+    vscale = mach * math.sqrt(0.6) / rms
+    p = 0.6 * rho / gamma
+    B = [gaussian_random_field(n, sd) for sd in seeds[4:7]]
+    b2 = float(np.mean(B[0] ** 2 + B[1] ** 2 + B[2] ** 2))
+    bscale = math.sqrt(2.0 * float(np.mean(p)) / beta / b2)
+    return mhd_conserved(rho, vel[0] * vscale, vel[1] * vscale, vel[2] * vscale, p,
+                         B[0] * bscale, B[1] * bscale, B[2] * bscale, gamma=gamma)
+
+
+def mhd_random_box(nx, ny, nz, seed=0, gamma=GAMMA, generic=True):
+    """Small periodic (9, nz, ny, nx) MHD test state: a few random Fourier
+    modes in every primitive (density and pressure kept positive), magnetic
+    field of order one and psi of order 0.1, for parity and invariance tests."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny,
+                          (np.arange(nx) + 0.5) / nx, indexing="ij")
+
+    def field(amp, base=0.0):
+        f = np.full(x.shape, base)
+        for _ in range(3):
+            k = _random_wavevector(rng, 2, generic=generic)
+            ph = rng.uniform(0, 2 * np.pi)
+            f += amp * rng.uniform(0.3, 1.0) * np.sin(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+        return f
+
+    rho = field(0.15, 1.0)
+    p = field(0.15, 1.0)
+    v = [field(0.3) for _ in range(3)]
+    B = [field(0.4, rng.uniform(-0.5, 0.5)) for _ in range(3)]
+    psi = field(0.1)
+    return mhd_conserved(rho, v[0], v[1], v[2], p, B[0], B[1], B[2], psi=psi, gamma=gamma)

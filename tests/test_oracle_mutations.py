@@ -16,7 +16,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
-FWD, ADJ = "godunov_oracle.c", "godunov_oracle_adjoint.c"
+FWD, ADJ, MHD = "godunov_oracle.c", "godunov_oracle_adjoint.c", "mhd_oracle.c"
+PINS = {FWD: "test_oracle_pins.py", ADJ: "test_oracle_pins.py", MHD: "test_mhd_oracle_pins.py"}
 
 # (file, text, replacement, the mistake it plants)
 MUTATIONS = [
@@ -44,13 +45,27 @@ MUTATIONS = [
      "adjoint of the pressure-gradient term"),
     (ADJ, "Lb[0] += mLb * (SL - L[1]);", "Lb[0] += mLb * (SR - L[1]);",
      "adjoint of the left wave mass flux"),
+    (MHD, "- (WR[8] - WL[8]) / (2.0 * ch);", "+ (WR[8] - WL[8]) / (2.0 * ch);",
+     "GLM normal field: sign of the psi jump"),
+    (MHD, "vs = v - By * t;", "vs = v + By * t;", "HLLD star transverse velocity sign"),
+    (MHD, "double q = (rho * (S - u) * (S - u) - Bn * Bn) / den;",
+     "double q = (rho * (S - u) * (S - u) + Bn * Bn) / den;", "HLLD star transverse field"),
+    (MHD, "Us[0][4] - sqr[0] * (uBs - uBss) * sgn", "Us[0][4] + sqr[0] * (uBs - uBss) * sgn",
+     "HLLD left double-star energy sign"),
+    (MHD, "un * B[k] - vel[k] * Bn;", "un * B[k] + vel[k] * Bn;", "induction flux sign"),
+    (MHD, "rho * un * vel[k] - Bn * B[k]", "rho * un * vel[k] + Bn * B[k]", "magnetic tension sign"),
+    (MHD, "4.0 * a2 * bn2", "2.0 * a2 * bn2", "fast magnetosonic speed"),
+    (MHD, "(U[4] - kin - mag)", "(U[4] - kin)", "pressure ignores the magnetic energy"),
+    (MHD, "exp(-P->alpha", "exp(P->alpha", "psi damping grows instead"),
+    (MHD, "const double h = P->dt / (2.0 * P->dx);", "const double h = P->dt / P->dx;",
+     "full step instead of a half step in the predictor"),
 ]
 
 
 def _run_mutant(case):
     fname, text, repl, what = case
     with tempfile.TemporaryDirectory() as tmp:
-        for f in (FWD, ADJ):
+        for f in (FWD, ADJ, MHD):
             shutil.copy(os.path.join(ORACLE, f), tmp)
         path = os.path.join(tmp, fname)
         src = open(path).read()
@@ -67,7 +82,7 @@ def _run_mutant(case):
             return what, "mutant does not compile: " + build.stderr[-300:]
         env["ORACLE_LIB_DIR"] = tmp
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                            os.path.join(ROOT, "tests", PINS[fname])],
                            cwd=ROOT, env=env, capture_output=True, text=True)
         return what, ("caught" if r.returncode != 0 else "NOT CAUGHT")
 
