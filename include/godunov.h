@@ -167,10 +167,12 @@ int godunov_step_batched_cfl(gd_ctx *ctx, const gd_opts *opts, int npatch,
  * the derivative of the branch the forward step takes is used. Every
  * element of lam_in is written exactly once (gather form, deterministic).
  * GD_F64 only (GD_E_UNSUPPORTED otherwise); lam_in must not overlap any
- * input (GD_E_ARG). The library keeps a device scratch of about 320 bytes
- * per cell of the box extended by two layers, (nx+4)(ny+4)(nz+4), grown on
- * first use (the growth synchronises the device; GD_E_NOMEM if it fails);
- * boxes with 15 (nx+4)(ny+4)(nz+4) >= 2^31 return GD_E_UNSUPPORTED. */
+ * input (GD_E_ARG). The library keeps a device scratch of 324 bytes per
+ * cell of the scratch box -- the box itself when periodic, the box extended
+ * by two layers, (nx+4)(ny+4)(nz+4), when ghosted -- grown on first use
+ * (the growth synchronises the device; GD_E_NOMEM if it fails); boxes whose
+ * scratch box has 20 times its cell count at or above 2^31 (a periodic box
+ * above about 475^3) return GD_E_UNSUPPORTED. */
 int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
                          const void *u_in, const void *lam_out, const void *lam_bflux,
                          void *lam_in, double gamma, double dx, double dt, void *hip_stream);
@@ -215,6 +217,49 @@ int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
  * the tiling, so outputs are bitwise identical across configurations. */
 int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int shape_batched,
                   int zpolicy_batched);
+
+/* ------------------------------------------------------------ ideal MHD
+ *
+ * One unsplit MUSCL-Hancock step of ideal magnetohydrodynamics with
+ * hyperbolic-parabolic divergence cleaning, the equation set of the paper's
+ * Enzo GPU solver (Sec. 2, Sec. 4), on a PERIODIC box (opts->bc must be
+ * GD_PERIODIC, else GD_E_UNSUPPORTED; opts->riemann is ignored: the fluxes
+ * are HLLD). Units with mu0 = 1.
+ *   conserved U = (rho, rho u, rho v, rho w, E, Bx, By, Bz, psi),
+ *     E = p/(gamma-1) + rho |u|^2/2 + |B|^2/2; layout [9][nz][ny][nx];
+ *   primitive W = (rho, u, v, w, p, Bx, By, Bz, psi), rho and p floored;
+ *   undivided limited slopes of W (opts->limiter);
+ *   half step: the values at a cell's upper and lower faces along each axis,
+ *     W +- S_d/2 (floored), move by one increment
+ *     dU = -dt/(2dx) sum_d [F_d(W + S_d/2) - F_d(W - S_d/2)], F_d the
+ *     physical flux, in which the flux of B_d is psi and that of psi is
+ *     ch^2 B_d (generalised Lagrange multiplier, Dedner et al. 2002);
+ *   face flux: B_n* = (B_nL + B_nR)/2 - (psi_R - psi_L)/(2 ch) and
+ *     psi* = (psi_L + psi_R)/2 - ch (B_nR - B_nL)/2 give the fluxes of B_n
+ *     (psi*) and psi (ch^2 B_n*); the HLLD solver of Miyoshi & Kusano (2005)
+ *     with normal field B_n* on both sides and wave speeds
+ *     S_L = min(u_L - cf_L, u_R - cf_R), S_R = max(u_L + cf_L, u_R + cf_R)
+ *     (cf the fast magnetosonic speed) gives the other seven;
+ *   U' = U - dt/dx ((dF_x + dF_y) + dF_z), then psi' *= exp(-alpha ch dt/dx).
+ *
+ * dt and ch come from the host values, or from device scalars when dt_dev /
+ * ch_dev are not NULL (as written by cfl_dt_mhd). u_out must not overlap
+ * u_in (GD_E_ARG). The library keeps a device scratch of 81 values per cell,
+ * grown on first use (the growth synchronises the device; GD_E_NOMEM if it
+ * fails). Boxes with 9 nx ny nz >= 2^31 return GD_E_UNSUPPORTED. Every
+ * element of u_out is written once (deterministic). */
+int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
+                     void *u_out, double gamma, double dx, double dt, const double *dt_dev,
+                     double ch, const double *ch_dev, double alpha, void *hip_stream);
+
+/* Time step and cleaning speed of a periodic MHD box:
+ * dt = cfl dx / max over cells of sum_d (|u_d| + cf_d) into *dt_dev and
+ * ch = max over cells and axes of |u_d| + cf_d into *ch_dev (device scalars;
+ * either may be NULL, not both). The maxima are exact (order-independent);
+ * the state's primitives are floored as in the step. */
+int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u,
+               double gamma, double dx, double cfl, double *dt_dev, double *ch_dev,
+               void *hip_stream);
 
 #ifdef __cplusplus
 }

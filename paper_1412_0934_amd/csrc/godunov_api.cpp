@@ -34,13 +34,16 @@ struct gd_ctx {
     int device = 0;
     int num_cus = 0;
     std::string err;
-    // device counters: [0] floor hits, [1] cfl max bits; queue words follow
+    // device counters: [0] floor hits, [1] cfl max bits, [2] fused cfl max
+    // bits, [4..5] MHD speed maxima; queue words follow
     unsigned long long *d_u64 = nullptr;
     unsigned *d_u32 = nullptr;          // [0..1] work queue, [2] cfl done
     BatchCache batch;
     BatchCache cfl;                      // descriptor cache used by cfl_dt
     double *d_adj = nullptr;             // adjoint scratch (grown on demand)
     size_t adj_bytes = 0;
+    void *d_mhd = nullptr;               // MHD step scratch (grown on demand)
+    size_t mhd_bytes = 0;
     // tuned configuration per dtype (index 0: FP64, 1: FP32)
     int zlen_single[2] = { 32, 32 };
     int shape_single[2] = { gd::TILE_16x16, gd::TILE_16x16 };
@@ -281,9 +284,9 @@ int gd_create(gd_ctx **out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
     if (ctx->num_cus < 1) ctx->num_cus = 256;
-    e = hipMalloc((void **)&ctx->d_u64, 4 * sizeof(unsigned long long));
+    e = hipMalloc((void **)&ctx->d_u64, 8 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_u32, 4 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, 8 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(ctx->d_u32, 0, 4 * sizeof(unsigned));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -305,6 +308,7 @@ int gd_destroy(gd_ctx *ctx)
         if (c->d_cfl_items) (void)hipFree(c->d_cfl_items);
     }
     if (ctx->d_adj) (void)hipFree(ctx->d_adj);
+    if (ctx->d_mhd) (void)hipFree(ctx->d_mhd);
     if (ctx->d_u64) (void)hipFree(ctx->d_u64);
     if (ctx->d_u32) (void)hipFree(ctx->d_u32);
     delete ctx;
@@ -678,6 +682,81 @@ int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int
     ctx->zlen_single[dtype] = zlen_single;
     ctx->shape_batched[dtype] = shape_batched;
     ctx->zpolicy_batched[dtype] = zpolicy_batched;
+    return GD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, double gamma, double dx)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if (opts->bc != GD_PERIODIC)
+        return fail(ctx, GD_E_UNSUPPORTED, "the MHD step supports periodic boxes only");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, GD_E_ARG, "extents must be >= 1 (%d,%d,%d)", nx, ny, nz);
+    if (nx > 65535 * 64 || ny > 65535 * 4 || nz > 65535) return fail(ctx, GD_E_ARG, "extent too large");
+    // 54 face-state values per cell are addressed with 64-bit offsets, the
+    // cells of the box with 32-bit ones
+    if ((int64_t)nx * ny * nz * 9 > 0x7fffffffLL) return fail(ctx, GD_E_UNSUPPORTED, "box too large");
+    if (!(gamma > 1.0)) return fail(ctx, GD_E_ARG, "gamma must be > 1");
+    if (!(dx > 0.0)) return fail(ctx, GD_E_ARG, "dx must be > 0");
+    return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
+                     void *u_out, double gamma, double dx, double dt, const double *dt_dev,
+                     double ch, const double *ch_dev, double alpha, void *hip_stream)
+{
+    int r;
+    if ((r = check_mhd(ctx, opts, nx, ny, nz, gamma, dx))) return r;
+    if (!dt_dev && !(dt >= 0.0)) return fail(ctx, GD_E_ARG, "dt must be >= 0");
+    if (!ch_dev && !(ch > 0.0)) return fail(ctx, GD_E_ARG, "ch must be > 0");
+    if (!(alpha >= 0.0)) return fail(ctx, GD_E_ARG, "alpha must be >= 0");
+    if (!u_in || !u_out) return fail(ctx, GD_E_ARG, "u_in and u_out must not be NULL");
+    const size_t bytes = 9ull * nx * ny * nz * elem_size(opts);
+    if (overlap(u_in, bytes, u_out, bytes)) return fail(ctx, GD_E_ARG, "u_out overlaps u_in");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    const size_t need = gd::mhd_scratch_bytes(opts->dtype, nx, ny, nz);
+    if (need > ctx->mhd_bytes) {
+        // grow the scratch; work already queued may still use the old one
+        hipError_t he = hipDeviceSynchronize();
+        if (he != hipSuccess) return hip_fail(ctx, he, "MHD scratch");
+        if (ctx->d_mhd) (void)hipFree(ctx->d_mhd);
+        ctx->d_mhd = nullptr;
+        ctx->mhd_bytes = 0;
+        if (hipMalloc(&ctx->d_mhd, need) != hipSuccess)
+            return fail(ctx, GD_E_NOMEM, "MHD scratch of %zu bytes", need);
+        ctx->mhd_bytes = need;
+    }
+    gd::MhdScalars sc{ gamma, opts->rho_floor, opts->p_floor, dx, dt, ch, alpha };
+    int e = gd::launch_mhd_step(opts->dtype, opts->limiter, nx, ny, nz, u_in, u_out, sc, dt_dev,
+                                ch_dev, ctx->d_mhd, (hipStream_t)hip_stream);
+    if (e) return hip_fail(ctx, e, "godunov_step_mhd launch");
+    return GD_OK;
+}
+
+int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u,
+               double gamma, double dx, double cfl, double *dt_dev, double *ch_dev,
+               void *hip_stream)
+{
+    int r;
+    if ((r = check_mhd(ctx, opts, nx, ny, nz, gamma, dx))) return r;
+    if (!(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
+    if (!u) return fail(ctx, GD_E_ARG, "u must not be NULL");
+    if (!dt_dev && !ch_dev) return fail(ctx, GD_E_ARG, "dt_dev and ch_dev are both NULL");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    gd::MhdScalars sc{ gamma, opts->rho_floor, opts->p_floor, dx, 0.0, 0.0, 0.0 };
+    int e = gd::launch_mhd_speeds(opts->dtype, nx, ny, nz, u, sc, cfl, dt_dev, ch_dev,
+                                  ctx->d_u64 + 4, (hipStream_t)hip_stream);
+    if (e) return hip_fail(ctx, e, "cfl_dt_mhd launch");
     return GD_OK;
 }
 

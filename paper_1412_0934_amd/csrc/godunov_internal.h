@@ -88,4 +88,24 @@ int launch_adjoint(int limiter, int riemann, const PatchDesc &P, const double *u
 
 int max_resident_blocks(int dtype, int limiter, int riemann, int shape, int device);
 
+// Ideal MHD on a periodic box (godunov_mhd.hip).
+struct MhdScalars {
+    double gamma, rho_floor, p_floor, dx, dt, ch, alpha;
+};
+
+// Bytes of device scratch one MHD step of an nx x ny x nz box needs.
+size_t mhd_scratch_bytes(int dtype, int nx, int ny, int nz);
+
+// One step; dt_dev / ch_dev, when not null, replace sc.dt / sc.ch.
+int launch_mhd_step(int dtype, int limiter, int nx, int ny, int nz, const void *u_in, void *u_out,
+                    const MhdScalars &sc, const double *dt_dev, const double *ch_dev,
+                    void *scratch, hipStream_t s);
+
+// dt = cfl dx / max sum_d (|u_d| + cf_d) and ch = max_d (|u_d| + cf_d) into
+// device scalars (either may be null); acc: two zeroed 64-bit accumulators,
+// left zeroed again.
+int launch_mhd_speeds(int dtype, int nx, int ny, int nz, const void *u, const MhdScalars &sc,
+                      double cfl, double *dt_dev, double *ch_dev, unsigned long long *acc,
+                      hipStream_t s);
+
 }  // namespace gd

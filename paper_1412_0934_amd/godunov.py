@@ -10,6 +10,8 @@ Entry points (same names as the C ABI, see include/godunov.h):
     step_batched(...)                 many ghost-zoned patches, one launch
     step_adjoint(u, lam_out, ...)     reverse mode of step for a fixed dt
     cfl_dt(u, gamma, dx, cfl)         CFL time step as a device scalar
+    step_mhd(u, gamma, dx, dt, ch)    ideal-MHD step (HLLD + GLM) of a periodic box
+    cfl_dt_mhd(u, gamma, dx, cfl)     its time step and cleaning speed
     GodunovRollout                    torch.autograd.Function over K steps
                                       with checkpointed recomputation
 """
@@ -60,7 +62,7 @@ assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
 EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
            "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt",
            "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
-           "godunov_step_cfl", "godunov_step_batched_cfl")
+           "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "cfl_dt_mhd")
 
 _lib = None
 _lock = threading.Lock()
@@ -99,6 +101,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.gd_autotune_batched.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, dbl, vp, ip]
         lib.gd_get_config.argtypes = [vp, i32, ip, ip, ip, ip]
         lib.gd_set_config.argtypes = [vp, i32, i32, i32, i32, i32]
+        lib.godunov_step_mhd.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, vp, dbl, dbl, dbl, vp,
+                                         dbl, vp, dbl, vp]
+        lib.cfl_dt_mhd.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, dbl, dbl, dbl, vp, vp, vp]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -405,3 +410,55 @@ class GodunovRollout(torch.autograd.Function):
 
 def rollout(u0, gamma, dx, dt, nsteps, every=5, limiter="minmod", riemann="hllc"):
     return GodunovRollout.apply(u0, gamma, dx, dt, nsteps, every, limiter, riemann)
+
+
+# ------------------------------------------------------------ ideal MHD
+
+def _mhd_shape(u):
+    if u.dim() != 4 or u.shape[0] != 9:
+        raise ValueError(f"MHD state must have shape (9, z, y, x), got {tuple(u.shape)}")
+    return u.shape[3], u.shape[2], u.shape[1]
+
+
+def step_mhd(u, gamma, dx, dt=None, ch=None, *, dt_dev=None, ch_dev=None, alpha=0.1,
+             limiter="minmod", out=None, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None):
+    """One ideal-MHD step (HLLD + GLM cleaning) of the periodic box u
+    [9, nz, ny, nx]; dt and ch from host values or 1-element float64 device
+    tensors. Returns u_new."""
+    _check_tensor(u, "u")
+    nx, ny, nz = _mhd_shape(u)
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out", u.dtype)
+    if dt is None and dt_dev is None:
+        raise ValueError("give dt or dt_dev")
+    if ch is None and ch_dev is None:
+        raise ValueError("give ch or ch_dev")
+    for t, name in ((dt_dev, "dt_dev"), (ch_dev, "ch_dev")):
+        if t is not None:
+            _check_tensor(t, name, torch.float64)
+    ctx = context(u.device.index)
+    o = _opts(u.dtype, True, limiter, "hllc", rho_floor, p_floor)
+    ctx.check(ctx.lib.godunov_step_mhd(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u), _ptr(out),
+                                       float(gamma), float(dx), float(dt or 0.0), _ptr(dt_dev),
+                                       float(ch or 0.0), _ptr(ch_dev), float(alpha),
+                                       _stream(stream)))
+    return out
+
+
+def cfl_dt_mhd(u, gamma, dx, cfl=0.4, *, out_dt=None, out_ch=None, rho_floor=RHO_FLOOR,
+               p_floor=P_FLOOR, stream=None):
+    """(dt, ch) of the periodic MHD box u as 1-element float64 device tensors:
+    dt = cfl dx / max sum_d (|u_d| + cf_d), ch = max_d (|u_d| + cf_d)."""
+    _check_tensor(u, "u")
+    nx, ny, nz = _mhd_shape(u)
+    if out_dt is None:
+        out_dt = torch.empty(1, dtype=torch.float64, device=u.device)
+    if out_ch is None:
+        out_ch = torch.empty(1, dtype=torch.float64, device=u.device)
+    ctx = context(u.device.index)
+    o = _opts(u.dtype, True, "minmod", "hllc", rho_floor, p_floor)
+    ctx.check(ctx.lib.cfl_dt_mhd(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u), float(gamma),
+                                 float(dx), float(cfl), _ptr(out_dt), _ptr(out_ch),
+                                 _stream(stream)))
+    return out_dt, out_ch

@@ -100,15 +100,41 @@ def test_adjoint_rejects_fp32(lib):
     assert r == -4
 
 
-@pytest.mark.parametrize("n,expect", [(600, -4), (500, -1)])
+@pytest.mark.parametrize("n,expect", [(600, -4), (400, -1)])
 def test_adjoint_rejects_boxes_beyond_32bit_indexing(lib, n, expect):
-    """15 (n+4)^3 scratch entries must stay below 2^31: 600^3 is refused on
-    the host; 500^3 passes that check and stops at the NULL context."""
+    """The 20 n^3 doubles of a scratch record array must stay below 2^31
+    entries: 600^3 is refused on the host; 400^3 passes that check and stops
+    at the NULL context."""
     o = _opts(bc=1)
     r = lib.godunov_step_adjoint(None, ctypes.byref(o), n, n, n, 0, ctypes.c_void_p(1 << 40),
                                  ctypes.c_void_p(2 << 40), None, ctypes.c_void_p(3 << 40),
                                  5 / 3, 0.1, 0.01, None)
     assert r == expect
+
+
+@pytest.mark.parametrize("case,kw,expect", [
+    ("ghosted box", dict(bc=0), -4),
+    ("fp32 ok until the context", dict(dtype=1), -1),
+    ("bad dx", dict(dx=0.0), -1),
+    ("ch <= 0", dict(ch=0.0), -1),
+    ("negative alpha", dict(alpha=-1.0), -1),
+    ("aliased output", dict(u_out=0x1000 + 8), -1),
+])
+def test_mhd_step_rejects_bad_arguments(lib, case, kw, expect):
+    o = _opts(bc=kw.pop("bc", 1), dtype=kw.pop("dtype", 0))
+    a = dict(dx=0.1, ch=1.0, alpha=0.1, u_out=1 << 24)
+    a.update(kw)
+    r = lib.godunov_step_mhd(None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000),
+                             ctypes.c_void_p(a["u_out"]), 5 / 3, a["dx"], 0.01, None, a["ch"],
+                             None, a["alpha"], None)
+    assert r == expect, case
+
+
+def test_cfl_dt_mhd_needs_an_output(lib):
+    o = _opts(bc=1)
+    r = lib.cfl_dt_mhd(None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000), 5 / 3, 0.1, 0.4,
+                       None, None, None)
+    assert r == -1
 
 
 def test_create_without_device_fails_cleanly(lib):
