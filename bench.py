@@ -22,7 +22,7 @@ Prints one JSON line:
             backward pass of a checkpointed 20-step rollout against its forward
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
-                       [--no-adjoint] [--tile 8x8 --zlen 16] [--calibrate-copy]
+                       [--no-adjoint] [--no-mhd] [--tile 8x8 --zlen 16] [--calibrate-copy]
 """
 from __future__ import annotations
 
@@ -32,6 +32,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -198,6 +200,55 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
 bench_batched.cache = None
 
 
+def bench_mhd(torch, gd, steps=10, warmup=2, n=128):
+    """Ideal MHD (HLLD + GLM cleaning) on the 128^3 periodic turbulent box
+    (log-normal density, rms Mach 1, Gaussian random B at plasma beta 100):
+    per step one cfl_dt_mhd and one godunov_step_mhd with dt and the cleaning
+    speed in device scalars. Minimal traffic: the 9 FP64 conserved values
+    read and written once, 144 B per cell."""
+    from paper_1412_0934_amd import inputs
+    log(f"bench: MHD, {n}^3 turbulent box")
+    u0 = inputs.mhd_turbulent_box(n)
+    a = torch.from_numpy(u0).cuda()
+    b = torch.empty_like(a)
+    dx = 1.0 / n
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    ch = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one(src, dst):
+        gd.cfl_dt_mhd(src, GAMMA, dx, 0.4, out_dt=dt, out_ch=ch)
+        gd.step_mhd(src, GAMMA, dx, dt_dev=dt, ch_dev=ch, alpha=0.1, out=dst)
+
+    for i in range(warmup):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    a.copy_(torch.from_numpy(u0))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    last = (b if steps % 2 == 1 else a).cpu().numpy()
+
+    def div_b(u):
+        d = 0.0
+        for c, ax in ((5, 2), (6, 1), (7, 0)):
+            d = d + (np.roll(u[c], -1, axis=ax) - np.roll(u[c], 1, axis=ax)) / (2 * dx)
+        return float(np.sqrt(np.mean(d * d)))
+
+    cells = n ** 3
+    return {"workload": f"ideal MHD {n}^3 periodic, log-normal density, rms Mach 1, Gaussian "
+                        "random B at plasma beta 100, HLLD + GLM cleaning (alpha 0.1), minmod, "
+                        "FP64; per step cfl_dt_mhd + godunov_step_mhd, dt and ch on the device",
+            "ms_per_step": ms, "mcell_per_s": cells / (ms * 1e-3) / 1e6,
+            "bytes_per_step": 144 * cells, "achieved_gbs": 144 * cells / (ms * 1e-3) / 1e9,
+            "hbm_frac": 144 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "div_b_rms_start": div_b(u0), f"div_b_rms_after_{steps}_steps": div_b(last)}
+
+
 def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
     5% amplitude), fixed dt: one adjoint step against one forward step, and
@@ -338,6 +389,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -403,6 +455,8 @@ def main():
     if not args.no_batched:
         also["batched"] = [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
                            bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]
+    if not args.no_mhd:
+        also["mhd"] = bench_mhd(torch, gd)
     if not args.no_adjoint:
         also["adjoint"] = bench_adjoint(torch, gd)
     if also:
