@@ -42,8 +42,10 @@ if ROOT not in sys.path:
 GAMMA = 5.0 / 3.0
 HBM_PEAK_GBS = 8000.0
 METRIC = "Mcell-updates/s per Godunov step (plain vs batched), % HBM roofline; adjoint/fwd"
+# the step kernel's own code (its launch interface lives in godunov_internal.h,
+# whose other declarations do not change the kernel)
 KERNEL_SRC = [os.path.join(ROOT, "paper_1412_0934_amd", "csrc", f)
-              for f in ("godunov_kernels.hip", "godunov_math.h", "godunov_internal.h")]
+              for f in ("godunov_kernels.hip", "godunov_math.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_traffic.txt")
 
 
