@@ -244,13 +244,24 @@ int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int
  *
  * dt and ch come from the host values, or from device scalars when dt_dev /
  * ch_dev are not NULL (as written by cfl_dt_mhd). u_out must not overlap
- * u_in (GD_E_ARG). The library keeps a device scratch of 81 values per cell,
+ * u_in (GD_E_ARG). The library keeps a device scratch of 54 values per cell,
  * grown on first use (the growth synchronises the device; GD_E_NOMEM if it
  * fails). Boxes with 9 nx ny nz >= 2^31 return GD_E_UNSUPPORTED. Every
  * element of u_out is written once (deterministic). */
 int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
                      void *u_out, double gamma, double dx, double dt, const double *dt_dev,
                      double ch, const double *ch_dev, double alpha, void *hip_stream);
+
+/* godunov_step_mhd that also writes, from the state it produces, the next
+ * step's dt = cfl dx / max sum_d (|u_d| + cf_d) to *dt_next_dev and
+ * ch = max_d (|u_d| + cf_d) to *ch_next_dev (device scalars, either may be
+ * NULL but not both; they may be dt_dev and ch_dev themselves, which the
+ * step reads before it writes them), the same values cfl_dt_mhd gives for
+ * u_out. */
+int godunov_step_mhd_cfl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz,
+                         const void *u_in, void *u_out, double gamma, double dx, double dt,
+                         const double *dt_dev, double ch, const double *ch_dev, double alpha,
+                         double cfl, double *dt_next_dev, double *ch_next_dev, void *hip_stream);
 
 /* Time step and cleaning speed of a periodic MHD box:
  * dt = cfl dx / max over cells of sum_d (|u_d| + cf_d) into *dt_dev and

@@ -35,7 +35,7 @@ struct gd_ctx {
     int num_cus = 0;
     std::string err;
     // device counters: [0] floor hits, [1] cfl max bits, [2] fused cfl max
-    // bits, [4..5] MHD speed maxima; queue words follow
+    // bits, [4..5] MHD speed maxima, [6..7] fused MHD speed maxima
     unsigned long long *d_u64 = nullptr;
     unsigned *d_u32 = nullptr;          // [0..1] work queue, [2] cfl done
     BatchCache batch;
@@ -707,17 +707,19 @@ int check_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, double g
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
-                     void *u_out, double gamma, double dx, double dt, const double *dt_dev,
-                     double ch, const double *ch_dev, double alpha, void *hip_stream)
+int step_mhd_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
+                  void *u_out, double gamma, double dx, double dt, const double *dt_dev, double ch,
+                  const double *ch_dev, double alpha, double cfl, double *dt_next,
+                  double *ch_next, void *hip_stream)
 {
     int r;
     if ((r = check_mhd(ctx, opts, nx, ny, nz, gamma, dx))) return r;
     if (!dt_dev && !(dt >= 0.0)) return fail(ctx, GD_E_ARG, "dt must be >= 0");
     if (!ch_dev && !(ch > 0.0)) return fail(ctx, GD_E_ARG, "ch must be > 0");
     if (!(alpha >= 0.0)) return fail(ctx, GD_E_ARG, "alpha must be >= 0");
+    if ((dt_next || ch_next) && !(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
     if (!u_in || !u_out) return fail(ctx, GD_E_ARG, "u_in and u_out must not be NULL");
     const size_t bytes = 9ull * nx * ny * nz * elem_size(opts);
     if (overlap(u_in, bytes, u_out, bytes)) return fail(ctx, GD_E_ARG, "u_out overlaps u_in");
@@ -737,9 +739,33 @@ int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, c
     }
     gd::MhdScalars sc{ gamma, opts->rho_floor, opts->p_floor, dx, dt, ch, alpha };
     int e = gd::launch_mhd_step(opts->dtype, opts->limiter, nx, ny, nz, u_in, u_out, sc, dt_dev,
-                                ch_dev, ctx->d_mhd, (hipStream_t)hip_stream);
+                                ch_dev, ctx->d_mhd, cfl, dt_next, ch_next, ctx->d_u64 + 6,
+                                (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "godunov_step_mhd launch");
     return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int godunov_step_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u_in,
+                     void *u_out, double gamma, double dx, double dt, const double *dt_dev,
+                     double ch, const double *ch_dev, double alpha, void *hip_stream)
+{
+    return step_mhd_impl(ctx, opts, nx, ny, nz, u_in, u_out, gamma, dx, dt, dt_dev, ch, ch_dev,
+                         alpha, 0.0, nullptr, nullptr, hip_stream);
+}
+
+int godunov_step_mhd_cfl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz,
+                         const void *u_in, void *u_out, double gamma, double dx, double dt,
+                         const double *dt_dev, double ch, const double *ch_dev, double alpha,
+                         double cfl, double *dt_next_dev, double *ch_next_dev, void *hip_stream)
+{
+    if (!dt_next_dev && !ch_next_dev)
+        return fail(ctx, GD_E_ARG, "dt_next_dev and ch_next_dev are both NULL");
+    return step_mhd_impl(ctx, opts, nx, ny, nz, u_in, u_out, gamma, dx, dt, dt_dev, ch, ch_dev,
+                         alpha, cfl, dt_next_dev, ch_next_dev, hip_stream);
 }
 
 int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const void *u,

@@ -96,10 +96,14 @@ struct MhdScalars {
 // Bytes of device scratch one MHD step of an nx x ny x nz box needs.
 size_t mhd_scratch_bytes(int dtype, int nx, int ny, int nz);
 
-// One step; dt_dev / ch_dev, when not null, replace sc.dt / sc.ch.
+// One step; dt_dev / ch_dev, when not null, replace sc.dt / sc.ch. With
+// dt_next or ch_next not null the launch also writes the next step's
+// cfl dx / max sum_d (|u_d| + cf_d) and max_d (|u_d| + cf_d) of u_out there
+// (acc: two zeroed 64-bit accumulators, left zeroed again).
 int launch_mhd_step(int dtype, int limiter, int nx, int ny, int nz, const void *u_in, void *u_out,
                     const MhdScalars &sc, const double *dt_dev, const double *ch_dev,
-                    void *scratch, hipStream_t s);
+                    void *scratch, double cfl, double *dt_next, double *ch_next,
+                    unsigned long long *acc, hipStream_t s);
 
 // dt = cfl dx / max sum_d (|u_d| + cf_d) and ch = max_d (|u_d| + cf_d) into
 // device scalars (either may be null); acc: two zeroed 64-bit accumulators,

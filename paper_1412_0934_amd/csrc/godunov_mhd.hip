@@ -14,10 +14,12 @@
 // Kusano (2005) with that normal field gives the other seven fluxes; then
 // U' = U - dt/dx ((dF_x + dF_y) + dF_z) and psi' <- psi' exp(-alpha ch dt/dx).
 //
-// Three launches per step over a library-owned scratch: predict (one thread
-// per cell: 7-point stencil, slopes, half step, six predicted face states),
-// flux (one thread per face of one direction, three launches), update (one
-// thread per cell). Every value is written by one thread: deterministic.
+// Two launches per step over a library-owned scratch: predict (one thread per
+// cell: 7-point stencil, slopes, half step, six predicted face states) and a
+// flux sweep (z-marching column tiles: x and y faces through LDS, z faces in
+// registers, the update, and optionally the signal speeds of the new state).
+// Every value is written by one thread and the reductions are maxima:
+// deterministic.
 #include "godunov_internal.h"
 #include "godunov_math.h"
 
@@ -342,50 +344,163 @@ __global__ __launch_bounds__(256) void k_predict(Par<T> P, const T *__restrict__
     }
 }
 
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_flux(Par<T> P, const T *__restrict__ dyn,
-                                              const T *__restrict__ fs, T *__restrict__ fl)
+// ------------------------------------------------------------ flux sweep
+
+// A workgroup owns a 16 x 16 column tile and marches up a z-range. Per plane,
+// the predicted x-face states of the tile (and of one halo cell at each end
+// of a row) are staged in LDS, every x face of the tile is evaluated once
+// (faces on a tile border by both tiles) and its flux overwrites the left
+// state it read; each cell takes its x flux difference; the same for y; the
+// z face above a cell is evaluated in registers and serves the plane above
+// as its lower face; then the update, and optionally the signal speeds of
+// the new state for the next step's dt and cleaning speed.
+constexpr int MTX = 16, MTY = 16, MT = MTX * MTY;
+constexpr int MSLOT = (MTX + 1) * (MTY + 1);
+
+template <typename T>
+struct SweepSmem {
+    T st[2][NV][MSLOT];      // [0] left state, then the flux; [1] right state
+    double red[2][MT / 64];  // wave maxima of the speed reduction
+};
+
+template <typename T>
+__device__ __forceinline__ void load_state(const Par<T> &P, const T *__restrict__ fs, int d,
+                                           int side, int c, T W[NV])
 {
-    take_dynamic(P, dyn);
-    const int i = blockIdx.x * 64 + threadIdx.x % 64;
-    const int j = blockIdx.y * 4 + threadIdx.x / 64;
-    const int k = blockIdx.z;
-    if (i >= P.nx || j >= P.ny) return;
-    const int c = (k * P.ny + j) * P.nx + i;
-    const int cl = cell(P.nx, P.ny, P.nz, i - (D == 0), j - (D == 1), k - (D == 2));
-    T WL[NV], WR[NV], F[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        WL[q] = fs[(size_t)((D * 2 + 0) * NV + q) * P.n + cl];
-        WR[q] = fs[(size_t)((D * 2 + 1) * NV + q) * P.n + c];
+    for (int q = 0; q < NV; ++q) W[q] = fs[(size_t)((d * 2 + side) * NV + q) * P.n + c];
+}
+
+// Faces of one direction: slot s of the x pass is row s / (MTX+1), face
+// s % (MTX+1) of that row (its right cell is tile column s % (MTX+1)); slot s
+// of the y pass is column s % MTX, face s / MTX of that column.
+template <int D, typename T>
+__device__ __forceinline__ void sweep_pass(const Par<T> &P, const T *__restrict__ fs, int i, int j,
+                                           int k, int tx, int ty, SweepSmem<T> &sm, T dF[NV])
+{
+    constexpr int NS = D == 0 ? (MTX + 1) * MTY : MTX * (MTY + 1);
+    const int lo = D == 0 ? ty * (MTX + 1) + tx : ty * MTX + tx;        // the cell's lower face
+    const int hi = D == 0 ? lo + 1 : lo + MTX;                         // its upper face
+    const int c = cell(P.nx, P.ny, P.nz, i, j, k);
+    {
+        T W[NV];
+        load_state(P, fs, D, 1, c, W);              // right state of the lower face
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sm.st[1][q][lo] = W[q];
+        load_state(P, fs, D, 0, c, W);              // left state of the upper face
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sm.st[0][q][hi] = W[q];
+        // the halo cells below the first and above the last cell of the row
+        const int edge = D == 0 ? tx : ty;
+        if (edge == 0) {
+            load_state(P, fs, D, 0, cell(P.nx, P.ny, P.nz, i - (D == 0), j - (D == 1), k), W);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sm.st[0][q][lo] = W[q];
+        }
+        if (edge == (D == 0 ? MTX : MTY) - 1) {
+            load_state(P, fs, D, 1, cell(P.nx, P.ny, P.nz, i + (D == 0), j + (D == 1), k), W);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sm.st[1][q][hi] = W[q];
+        }
     }
-    face_flux<D>(P, WL, WR, F);
+    __syncthreads();
+    for (int t = threadIdx.x; t < NS; t += MT) {
+        T WL[NV], WR[NV], F[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) fl[(size_t)(D * NV + q) * P.n + c] = F[q];
+        for (int q = 0; q < NV; ++q) { WL[q] = sm.st[0][q][t]; WR[q] = sm.st[1][q][t]; }
+        face_flux<D>(P, WL, WR, F);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sm.st[0][q][t] = F[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) dF[q] = sm.st[0][q][hi] - sm.st[0][q][lo];
+    __syncthreads();
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(Par<T> P, const T *__restrict__ dyn,
-                                                const T *__restrict__ u, const T *__restrict__ fl,
-                                                T *__restrict__ out)
+__global__ __launch_bounds__(MT) void k_sweep(Par<T> P, const T *__restrict__ dyn,
+                                              const T *__restrict__ u, const T *__restrict__ fs,
+                                              T *__restrict__ out, int ntx, int nty, int zlen,
+                                              int nitem, int per_xcd,
+                                              unsigned long long *__restrict__ acc)
 {
+    __shared__ SweepSmem<T> sm;
     take_dynamic(P, dyn);
-    const int i = blockIdx.x * 64 + threadIdx.x % 64;
-    const int j = blockIdx.y * 4 + threadIdx.x / 64;
-    const int k = blockIdx.z;
-    if (i >= P.nx || j >= P.ny) return;
-    const int c = (k * P.ny + j) * P.nx + i;
-    const int cx = cell(P.nx, P.ny, P.nz, i + 1, j, k);
-    const int cy = cell(P.nx, P.ny, P.nz, i, j + 1, k);
-    const int cz = cell(P.nx, P.ny, P.nz, i, j, k + 1);
+    // workgroups are dealt to the eight XCDs in turn: give each XCD a
+    // contiguous range of work items, so that neighbouring tiles share its L2
+    const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (b >= nitem) return;
+    const int bx = b % ntx, br = b / ntx;
+    const int by = br % nty, bz = br / nty;
+    const int tx = threadIdx.x % MTX, ty = threadIdx.x / MTX;
+    const int i = bx * MTX + tx, j = by * MTY + ty;
+    const bool own = i < P.nx && j < P.ny;
+    const int k0 = bz * zlen, k1 = min(k0 + zlen, P.nz);
+
+    // flux through the z face below the first plane
+    T Flo[NV];
+    {
+        T WL[NV], WR[NV];
+        load_state(P, fs, 2, 0, cell(P.nx, P.ny, P.nz, i, j, k0 - 1), WL);
+        load_state(P, fs, 2, 1, cell(P.nx, P.ny, P.nz, i, j, k0), WR);
+        face_flux<2>(P, WL, WR, Flo);
+    }
+    double smax = 0.0, dmax = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        T dFx[NV], dFy[NV];
+        sweep_pass<0>(P, fs, i, j, k, tx, ty, sm, dFx);
+        sweep_pass<1>(P, fs, i, j, k, tx, ty, sm, dFy);
+        T Fhi[NV];
+        {
+            T WL[NV], WR[NV];
+            load_state(P, fs, 2, 0, cell(P.nx, P.ny, P.nz, i, j, k), WL);
+            load_state(P, fs, 2, 1, cell(P.nx, P.ny, P.nz, i, j, k + 1), WR);
+            face_flux<2>(P, WL, WR, Fhi);
+        }
+        if (own) {
+            const int c = (k * P.ny + j) * P.nx + i;
+            T U[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const T dFx = fl[(size_t)(0 * NV + q) * P.n + cx] - fl[(size_t)(0 * NV + q) * P.n + c];
-        const T dFy = fl[(size_t)(1 * NV + q) * P.n + cy] - fl[(size_t)(1 * NV + q) * P.n + c];
-        const T dFz = fl[(size_t)(2 * NV + q) * P.n + cz] - fl[(size_t)(2 * NV + q) * P.n + c];
-        T v = u[(size_t)q * P.n + c] - P.c * ((dFx + dFy) + dFz);
-        if (q == 8) v *= P.damp;
-        out[(size_t)q * P.n + c] = v;
+            for (int q = 0; q < NV; ++q) {
+                const T dFz = Fhi[q] - Flo[q];
+                T v = u[(size_t)q * P.n + c] - P.c * ((dFx[q] + dFy[q]) + dFz);
+                if (q == 8) v *= P.damp;
+                out[(size_t)q * P.n + c] = v;
+                U[q] = v;
+            }
+            if (acc) {
+                T W[NV];
+                to_prim(P, U, W);
+                double sum = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double v = (double)fabs(W[1 + d]) + (double)fast_speed(P, W, W[5 + d]);
+                    sum += v;
+                    dmax = fmax(dmax, v);
+                }
+                smax = fmax(smax, sum);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Flo[q] = Fhi[q];
+    }
+    if (!acc) return;
+    // block maxima: wave maxima by shuffles, then the first wave over the waves
+    for (int o = 32; o > 0; o >>= 1) {
+        smax = fmax(smax, __shfl_xor(smax, o));
+        dmax = fmax(dmax, __shfl_xor(dmax, o));
+    }
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) { sm.red[0][w] = smax; sm.red[1][w] = dmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < MT / 64; ++q) {
+            smax = fmax(smax, sm.red[0][q]);
+            dmax = fmax(dmax, sm.red[1][q]);
+        }
+        atomicMax(&acc[0], (unsigned long long)__double_as_longlong(smax));
+        atomicMax(&acc[1], (unsigned long long)__double_as_longlong(dmax));
     }
 }
 
@@ -460,14 +575,15 @@ size_t mhd_scratch_bytes(int dtype, int nx, int ny, int nz)
 {
     const size_t n = (size_t)nx * ny * nz;
     const size_t el = dtype == 0 ? 8 : 4;
-    // six face states and three face fluxes of 9 values per cell, plus the
-    // step's device-side parameters
-    return (6 * 9 + 3 * 9) * n * el + 512;
+    // six face states of 9 values per cell, plus the step's device-side
+    // parameters
+    return 6 * 9 * n * el + 512;
 }
 
 template <typename T>
 static int run_mhd(int limiter, int nx, int ny, int nz, const void *u_in, void *u_out,
                    const MhdScalars &sc, const double *dt_dev, const double *ch_dev, void *scratch,
+                   double cfl, double *dt_next, double *ch_next, unsigned long long *acc,
                    hipStream_t st)
 {
     mhd::Par<T> P{};
@@ -480,10 +596,9 @@ static int run_mhd(int limiter, int nx, int ny, int nz, const void *u_in, void *
     P.damp = (T)exp(-sc.alpha * sc.ch * sc.dt / sc.dx);
     const size_t n = (size_t)P.n;
     T *fs = (T *)scratch;
-    T *fl = fs + 54 * n;
     T *dyn = nullptr;
     if (dt_dev || ch_dev) {
-        dyn = (T *)(((uintptr_t)(fl + 27 * n) + 255) & ~(uintptr_t)255);
+        dyn = (T *)(((uintptr_t)(fs + 54 * n) + 255) & ~(uintptr_t)255);
         hipLaunchKernelGGL(mhd::k_params<T>, dim3(1), dim3(64), 0, st, dyn, dt_dev, ch_dev, sc.dt,
                            sc.ch, sc.dx, sc.alpha);
     }
@@ -495,20 +610,32 @@ static int run_mhd(int limiter, int nx, int ny, int nz, const void *u_in, void *
     case 2: hipLaunchKernelGGL((mhd::k_predict<T, 2>), grid, block, 0, st, P, dyn, u, fs); break;
     default: hipLaunchKernelGGL((mhd::k_predict<T, 0>), grid, block, 0, st, P, dyn, u, fs); break;
     }
-    hipLaunchKernelGGL((mhd::k_flux<T, 0>), grid, block, 0, st, P, dyn, fs, fl);
-    hipLaunchKernelGGL((mhd::k_flux<T, 1>), grid, block, 0, st, P, dyn, fs, fl);
-    hipLaunchKernelGGL((mhd::k_flux<T, 2>), grid, block, 0, st, P, dyn, fs, fl);
-    hipLaunchKernelGGL(mhd::k_update<T>, grid, block, 0, st, P, dyn, u, fl, out);
+    // z-ranges: about 1024 work items, at least 2 planes each
+    const int ntx = (nx + mhd::MTX - 1) / mhd::MTX, nty = (ny + mhd::MTY - 1) / mhd::MTY;
+    int nseg = (1024 + ntx * nty - 1) / (ntx * nty);
+    nseg = nseg < 1 ? 1 : (nseg > (nz + 1) / 2 ? (nz + 1) / 2 : nseg);
+    const int zlen = (nz + nseg - 1) / nseg;
+    nseg = (nz + zlen - 1) / zlen;
+    const int nitem = ntx * nty * nseg, per_xcd = (nitem + 7) / 8;
+    unsigned long long *a = dt_next || ch_next ? acc : nullptr;
+    hipLaunchKernelGGL(mhd::k_sweep<T>, dim3(8 * per_xcd), dim3(mhd::MT), 0, st, P, dyn, u, fs, out,
+                       ntx, nty, zlen, nitem, per_xcd, a);
+    if (a)
+        hipLaunchKernelGGL(mhd::k_speeds_finish, dim3(1), dim3(64), 0, st, cfl, sc.dx, a, dt_next,
+                           ch_next);
     return (int)hipGetLastError();
 }
 
 int launch_mhd_step(int dtype, int limiter, int nx, int ny, int nz, const void *u_in, void *u_out,
                     const MhdScalars &sc, const double *dt_dev, const double *ch_dev,
-                    void *scratch, hipStream_t s)
+                    void *scratch, double cfl, double *dt_next, double *ch_next,
+                    unsigned long long *acc, hipStream_t s)
 {
     if (dtype == 0)
-        return run_mhd<double>(limiter, nx, ny, nz, u_in, u_out, sc, dt_dev, ch_dev, scratch, s);
-    return run_mhd<float>(limiter, nx, ny, nz, u_in, u_out, sc, dt_dev, ch_dev, scratch, s);
+        return run_mhd<double>(limiter, nx, ny, nz, u_in, u_out, sc, dt_dev, ch_dev, scratch, cfl,
+                               dt_next, ch_next, acc, s);
+    return run_mhd<float>(limiter, nx, ny, nz, u_in, u_out, sc, dt_dev, ch_dev, scratch, cfl,
+                          dt_next, ch_next, acc, s);
 }
 
 template <typename T>

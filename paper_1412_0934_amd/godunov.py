@@ -62,7 +62,8 @@ assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
 EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
            "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt",
            "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
-           "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "cfl_dt_mhd")
+           "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "godunov_step_mhd_cfl",
+           "cfl_dt_mhd")
 
 _lib = None
 _lock = threading.Lock()
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.godunov_step_mhd.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, vp, dbl, dbl, dbl, vp,
                                          dbl, vp, dbl, vp]
         lib.cfl_dt_mhd.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, dbl, dbl, dbl, vp, vp, vp]
+        lib.godunov_step_mhd_cfl.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, vp, dbl, dbl, dbl,
+                                             vp, dbl, vp, dbl, dbl, vp, vp, vp]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -421,10 +424,13 @@ def _mhd_shape(u):
 
 
 def step_mhd(u, gamma, dx, dt=None, ch=None, *, dt_dev=None, ch_dev=None, alpha=0.1,
-             limiter="minmod", out=None, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None):
+             limiter="minmod", out=None, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None,
+             cfl=None, dt_next=None, ch_next=None):
     """One ideal-MHD step (HLLD + GLM cleaning) of the periodic box u
     [9, nz, ny, nx]; dt and ch from host values or 1-element float64 device
-    tensors. Returns u_new."""
+    tensors. With cfl and dt_next / ch_next (1-element float64 device tensors,
+    which may be dt_dev / ch_dev) the launch also writes the next step's dt
+    and cleaning speed from u_new. Returns u_new."""
     _check_tensor(u, "u")
     nx, ny, nz = _mhd_shape(u)
     if out is None:
@@ -439,10 +445,22 @@ def step_mhd(u, gamma, dx, dt=None, ch=None, *, dt_dev=None, ch_dev=None, alpha=
             _check_tensor(t, name, torch.float64)
     ctx = context(u.device.index)
     o = _opts(u.dtype, True, limiter, "hllc", rho_floor, p_floor)
-    ctx.check(ctx.lib.godunov_step_mhd(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u), _ptr(out),
-                                       float(gamma), float(dx), float(dt or 0.0), _ptr(dt_dev),
-                                       float(ch or 0.0), _ptr(ch_dev), float(alpha),
-                                       _stream(stream)))
+    if dt_next is None and ch_next is None:
+        ctx.check(ctx.lib.godunov_step_mhd(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u),
+                                           _ptr(out), float(gamma), float(dx), float(dt or 0.0),
+                                           _ptr(dt_dev), float(ch or 0.0), _ptr(ch_dev),
+                                           float(alpha), _stream(stream)))
+        return out
+    for t, name in ((dt_next, "dt_next"), (ch_next, "ch_next")):
+        if t is not None:
+            _check_tensor(t, name, torch.float64)
+    if cfl is None:
+        raise ValueError("dt_next / ch_next need cfl")
+    ctx.check(ctx.lib.godunov_step_mhd_cfl(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u),
+                                           _ptr(out), float(gamma), float(dx), float(dt or 0.0),
+                                           _ptr(dt_dev), float(ch or 0.0), _ptr(ch_dev),
+                                           float(alpha), float(cfl), _ptr(dt_next), _ptr(ch_next),
+                                           _stream(stream)))
     return out
 
 

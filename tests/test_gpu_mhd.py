@@ -78,6 +78,28 @@ def test_device_cfl_and_cleaning_speed(gd):
     assert np.array_equal(a, b)
 
 
+def test_fused_cfl_writes_the_next_dt_and_cleaning_speed(gd):
+    """godunov_step_mhd_cfl writes the same state as godunov_step_mhd, and as
+    dt_next / ch_next the values cfl_dt_mhd and the oracle give for that
+    state; dt_next and ch_next may be the scalars the step reads."""
+    import torch
+    u = inputs.mhd_random_box(13, 7, 10, seed=8)
+    dx = 1.0 / 13
+    ud = dev(u)
+    dt, ch = gd.cfl_dt_mhd(ud, G, dx, 0.4)
+    say("mhd plain step")
+    plain = host(gd.step_mhd(ud, G, dx, dt_dev=dt, ch_dev=ch))
+    say("mhd fused step")
+    fused = host(gd.step_mhd(ud, G, dx, dt_dev=dt, ch_dev=ch, cfl=0.4, dt_next=dt, ch_next=ch))
+    assert np.array_equal(plain, fused)
+    ref_dt, ref_ch = mhd.cfl(fused, G, dx, 0.4)
+    got_dt, got_ch = float(host(dt)[0]), float(host(ch)[0])
+    assert abs(got_dt - ref_dt) <= 1e-14 * ref_dt
+    assert abs(got_ch - ref_ch) <= 1e-14 * ref_ch
+    dt2, ch2 = gd.cfl_dt_mhd(dev(fused), G, dx, 0.4)
+    assert float(host(dt2)[0]) == got_dt and float(host(ch2)[0]) == got_ch
+
+
 def test_free_stream_is_preserved_bit_for_bit(gd):
     n = 8
     one = np.ones((n, n + 1, n + 2))
@@ -106,8 +128,9 @@ def _div_b(u, dx):
 
 
 def test_turbulent_box_128_ten_steps(gd):
-    """The 128^3 MHD workload as the benchmark runs it: per step one
-    cfl_dt_mhd and one godunov_step_mhd with dt and ch on the device. The
+    """The 128^3 MHD workload as the benchmark runs it: one cfl_dt_mhd, then
+    per step one godunov_step_mhd_cfl that reads dt and ch from device scalars
+    and writes the next step's into them. The
     first step is checked against the oracle at full size, all ten against
     the oracle's own ten-step run, and div B must decay."""
     import torch
@@ -124,9 +147,10 @@ def test_turbulent_box_128_ten_steps(gd):
     dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
     ch_dev = torch.empty(1, dtype=torch.float64, device="cuda")
     first = None
+    gd.cfl_dt_mhd(a, G, dx, 0.4, out_dt=dt_dev, out_ch=ch_dev)
     for s in range(10):
-        gd.cfl_dt_mhd(a, G, dx, 0.4, out_dt=dt_dev, out_ch=ch_dev)
-        gd.step_mhd(a, G, dx, dt_dev=dt_dev, ch_dev=ch_dev, alpha=0.1, out=b)
+        gd.step_mhd(a, G, dx, dt_dev=dt_dev, ch_dev=ch_dev, alpha=0.1, out=b, cfl=0.4,
+                    dt_next=dt_dev, ch_next=ch_dev)
         if s == 0:
             first = host(b)
         a, b = b, a
