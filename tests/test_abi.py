@@ -130,6 +130,14 @@ def test_mhd_step_rejects_bad_arguments(lib, case, kw, expect):
     assert r == expect, case
 
 
+def test_fused_mhd_step_needs_an_output_and_a_cfl(lib):
+    o = _opts(bc=1)
+    args = [None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000), ctypes.c_void_p(1 << 24),
+            5 / 3, 0.1, 0.01, None, 1.0, None, 0.1]
+    assert lib.godunov_step_mhd_cfl(*args, 0.4, None, None, None) == -1
+    assert lib.godunov_step_mhd_cfl(*args, 0.0, ctypes.c_void_p(1 << 26), None, None) == -1
+
+
 def test_cfl_dt_mhd_needs_an_output(lib):
     o = _opts(bc=1)
     r = lib.cfl_dt_mhd(None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000), 5 / 3, 0.1, 0.4,
