@@ -597,14 +597,17 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
                             gd::TILE_24x8 };
     const int zlens[3] = { 16, 32, 64 };
     const int keep_shape = ctx->shape_single[dt_i], keep_zlen = ctx->zlen_single[dt_i];
-    float best = 1e30f;
-    int best_i = -1;
-    for (int si = 0; si < 5; ++si)
-        for (int zi = 0; zi < 3; ++zi) {
-            ctx->shape_single[dt_i] = shapes[si];
-            ctx->zlen_single[dt_i] = zlens[zi];
+    // round 0 runs every candidate once (clocks and caches settle); rounds 1
+    // and 2 time each candidate over 4 calls; a candidate's time is its best
+    // round, so a transient slowdown does not decide the choice
+    float best_ms[15];
+    for (float &m : best_ms) m = 1e30f;
+    for (int round = 0; round < 3; ++round)
+        for (int c = 0; c < 15; ++c) {
+            ctx->shape_single[dt_i] = shapes[c / 3];
+            ctx->zlen_single[dt_i] = zlens[c % 3];
             float ms = 0.f;
-            r = time_calls(ctx, (hipStream_t)hip_stream, 3, [&] {
+            r = time_calls(ctx, (hipStream_t)hip_stream, round == 0 ? 1 : 4, [&] {
                 return godunov_step(ctx, opts, nx, ny, nz, ng, u_in, u_out, nullptr, gamma, dx,
                                     dt, nullptr, hip_stream);
             }, &ms);
@@ -613,8 +616,11 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
                 ctx->zlen_single[dt_i] = keep_zlen;
                 return r;
             }
-            if (ms < best) { best = ms; best_i = si * 3 + zi; }
+            if (round > 0) best_ms[c] = std::min(best_ms[c], ms);
         }
+    int best_i = 0;
+    for (int c = 1; c < 15; ++c)
+        if (best_ms[c] < best_ms[best_i]) best_i = c;
     ctx->shape_single[dt_i] = shapes[best_i / 3];
     ctx->zlen_single[dt_i] = zlens[best_i % 3];
     if (choice) *choice = best_i;
@@ -632,14 +638,16 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
                             gd::TILE_24x8 };
     const int keep_shape = ctx->shape_batched[dt_i], keep_pol = ctx->zpolicy_batched[dt_i];
-    float best = 1e30f;
-    int best_i = -1;
-    for (int si = 0; si < 5; ++si)
-        for (int zp = 0; zp < 3; ++zp) {
-            ctx->shape_batched[dt_i] = shapes[si];
-            ctx->zpolicy_batched[dt_i] = zp;
+    // the same protocol as gd_autotune_step: a warm-up round, then the best
+    // of two timed rounds per candidate
+    float best_ms[15];
+    for (float &m : best_ms) m = 1e30f;
+    for (int round = 0; round < 3; ++round)
+        for (int c = 0; c < 15; ++c) {
+            ctx->shape_batched[dt_i] = shapes[c / 3];
+            ctx->zpolicy_batched[dt_i] = c % 3;
             float ms = 0.f;
-            r = time_calls(ctx, (hipStream_t)hip_stream, 3, [&] {
+            r = time_calls(ctx, (hipStream_t)hip_stream, round == 0 ? 1 : 3, [&] {
                 return godunov_step_batched(ctx, opts, npatch, patches, u_in_base, u_out_base,
                                             bflux_base, nullptr, gamma, hip_stream);
             }, &ms);
@@ -648,8 +656,11 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
                 ctx->zpolicy_batched[dt_i] = keep_pol;
                 return r;
             }
-            if (ms < best) { best = ms; best_i = si * 3 + zp; }
+            if (round > 0) best_ms[c] = std::min(best_ms[c], ms);
         }
+    int best_i = 0;
+    for (int c = 1; c < 15; ++c)
+        if (best_ms[c] < best_ms[best_i]) best_i = c;
     ctx->shape_batched[dt_i] = shapes[best_i / 3];
     ctx->zpolicy_batched[dt_i] = best_i % 3;
     if (choice) *choice = best_i;
