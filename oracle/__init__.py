@@ -5,7 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package. The GPU library never
 loads it, and it shares no code with the GPU path: the C sources here are
 compiled by gcc into ``liboracle.so`` (double), ``liboracle_cs.so``
 (double complex, a complex-step tangent-linear model of the same forward code)
-and ``libmhd_oracle.so`` (the ideal-MHD step, wrapped by ``oracle.mhd``).
+and ``libmhd_oracle.so`` (the ideal-MHD step, wrapped by ``oracle.mhd``);
+``oracle.amr`` (Python) runs one step of a two-level hierarchy -- ghost fill,
+refluxing, averaging down -- around the single-patch step.
 
 The step follows the paper's method family (Sec. 2: Euler equations of an
 ideal gas, piecewise-linear Godunov scheme; Sec. 3: ghost-zoned patches;

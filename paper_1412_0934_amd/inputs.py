@@ -384,3 +384,91 @@ def mhd_random_box(nx, ny, nz, seed=0, gamma=GAMMA, generic=True):
     B = [field(0.4, rng.uniform(-0.5, 0.5)) for _ in range(3)]
     psi = field(0.1)
     return mhd_conserved(rho, v[0], v[1], v[2], p, B[0], B[1], B[2], psi=psi, gamma=gamma)
+
+
+# ------------------------------------------------------------ two-level AMR
+
+@dataclass
+class Hierarchy:
+    """A periodic coarse box of nc^3 cells and fine patches refined by 2.
+    Fine patch p covers the coarse cells [lo[p], lo[p] + n[p]/2); n[p] are its
+    interior extents in fine cells (x, y, z), even. The fine patches live in a
+    Batch (two ghost layers) whose ghost cells are left NaN: filling them is
+    part of the step."""
+    nc: int
+    coarse: np.ndarray          # (5, nc, nc, nc)
+    lo: np.ndarray              # (P, 3) int, (x, y, z) coarse indices
+    n: np.ndarray               # (P, 3) int, (nx, ny, nz) fine cells
+    fine: Batch
+
+    @property
+    def dx_coarse(self):
+        return 1.0 / self.nc
+
+
+def _smooth_state(rng, gamma):
+    """A smooth periodic analytic state on the unit box (rho, p = 1 +- 0.2,
+    |v| <= 0.3), returned as a function of cell-centre coordinates."""
+    ks = [rng.integers(-2, 3, size=3) for _ in range(5)]
+    for k in ks:
+        if not np.any(k):
+            k[0] = 1
+    ph = rng.uniform(0, 2 * math.pi, size=5)
+    amp = [0.2, 0.3, 0.3, 0.3, 0.2]
+
+    def at(X, Y, Z):
+        f = [amp[i] * np.sin(2 * math.pi * (ks[i][0] * X + ks[i][1] * Y + ks[i][2] * Z) + ph[i])
+             for i in range(5)]
+        return conserved(1.0 + f[0], f[1], f[2], f[3], 1.0 + f[4], gamma)
+
+    return at
+
+
+def amr_hierarchy(nc=32, nfine=8, seed=11, gamma=GAMMA, max_size=5, touch=0.5):
+    """Seeded two-level hierarchy: the same smooth analytic state sampled at
+    the coarse cell centres and at the fine cell centres of each patch.
+    Patches are random boxes of 2..max_size coarse cells per axis, disjoint,
+    inside [2, nc - 2) (no periodic crossing); with probability `touch` a new
+    patch is placed against an existing one, so fine-fine faces occur."""
+    rng = np.random.default_rng(seed)
+    at = _smooth_state(rng, gamma)
+    owner = -np.ones((nc, nc, nc), dtype=np.int64)          # [x][y][z]
+    los, sizes = [], []
+    tries = 0
+    while len(los) < nfine and tries < 5000:
+        tries += 1
+        size = rng.integers(2, max_size + 1, size=3)
+        if los and rng.uniform() < touch:
+            q = rng.integers(len(los))
+            axis = rng.integers(3)
+            lo = los[q].copy()
+            lo[axis] = los[q][axis] + sizes[q][axis] if rng.uniform() < 0.5 else los[q][axis] - size[axis]
+            for a in range(3):
+                if a != axis:
+                    lo[a] = los[q][a] + rng.integers(-1, 2)
+        else:
+            lo = rng.integers(2, nc - 2 - size + 1, size=3) if np.all(nc - 2 - size + 1 > 2) else None
+            if lo is None:
+                continue
+        if np.any(lo < 2) or np.any(lo + size > nc - 2):
+            continue
+        box = owner[lo[0]:lo[0] + size[0], lo[1]:lo[1] + size[1], lo[2]:lo[2] + size[2]]
+        if np.any(box >= 0):
+            continue
+        box[...] = len(los)
+        los.append(np.asarray(lo))
+        sizes.append(np.asarray(size))
+    lo = np.array(los, dtype=np.int64).reshape(-1, 3)
+    n = 2 * np.array(sizes, dtype=np.int64).reshape(-1, 3)
+    xc = (np.arange(nc) + 0.5) / nc
+    coarse = at(xc[None, None, :], xc[None, :, None], xc[:, None, None])
+    fine = batch_layout(n, 2, 0.5 / nc)
+    fine.u_in[:] = np.nan
+    for p in range(len(lo)):
+        nx, ny, nz = (int(v) for v in n[p])
+        X = (2 * lo[p][0] + np.arange(nx) + 0.5) / (2 * nc)
+        Y = (2 * lo[p][1] + np.arange(ny) + 0.5) / (2 * nc)
+        Z = (2 * lo[p][2] + np.arange(nz) + 0.5) / (2 * nc)
+        fine.patch_in(p)[:, 2:-2, 2:-2, 2:-2] = at(X[None, None, :], Y[None, :, None],
+                                                   Z[:, None, None])
+    return Hierarchy(nc, coarse, lo, n, fine)

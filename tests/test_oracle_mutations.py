@@ -17,7 +17,9 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 FWD, ADJ, MHD = "godunov_oracle.c", "godunov_oracle_adjoint.c", "mhd_oracle.c"
-PINS = {FWD: "test_oracle_pins.py", ADJ: "test_oracle_pins.py", MHD: "test_mhd_oracle_pins.py"}
+AMR = "amr.py"
+PINS = {FWD: "test_oracle_pins.py", ADJ: "test_oracle_pins.py", MHD: "test_mhd_oracle_pins.py",
+        AMR: "test_amr_oracle_pins.py"}
 
 # (file, text, replacement, the mistake it plants)
 MUTATIONS = [
@@ -59,11 +61,31 @@ MUTATIONS = [
     (MHD, "exp(-P->alpha", "exp(P->alpha", "psi damping grows instead"),
     (MHD, "const double h = P->dt / (2.0 * P->dx);", "const double h = P->dt / P->dx;",
      "full step instead of a half step in the predictor"),
+    (AMR, "corr = c * (Ff - Fc) if side else c * (Fc - Ff)",
+     "corr = c * (Fc - Ff) if side else c * (Ff - Fc)", "reflux correction sign"),
+    (AMR, "blk = sheet[:, loc[2]:loc[2] + 2, loc[1]:loc[1] + 2]",
+     "blk = sheet[:, loc[1]:loc[1] + 2, loc[2]:loc[2] + 2]", "x sheet read transposed"),
+    (AMR, "right = out_cell if side else cell", "right = cell if side else out_cell",
+     "coarse flux taken at the wrong face"),
+    (AMR, "o[d] = (c[d] + (1 if side else -1)) % nc", "o[d] = (c[d] + 1) % nc",
+     "lower-side interface corrects the wrong cell"),
+    (AMR, "c = dt / dxc\n", "c = dt / (2 * dxc)\n", "reflux scaled by the fine spacing"),
+    (AMR, "(blk[:, 1, 0] + blk[:, 1, 1])) * 0.25", "(blk[:, 1, 0] + blk[:, 1, 1])) * 0.5",
+     "fine flux summed instead of averaged"),
+    (AMR, "(z[0] + z[1]) * 0.125", "(z[0] + z[1]) * 0.25", "average down over four children"),
+    (AMR, "coarse[:, gz // 2, gy // 2, gx // 2]", "coarse[:, gy // 2, gz // 2, gx // 2]",
+     "coarse parent with y and z swapped"),
+    (AMR, "gx = (2 * h.lo[p][0] + ii - 2) % m", "gx = (2 * h.lo[p][0] + ii - 1) % m",
+     "ghost position off by one"),
+    (AMR, "gz - 2 * h.lo[q][2] + 2,", "gz - 2 * h.lo[q][2] + 1,", "fine source cell off by one"),
+    (AMR, "dxc / 2, dt,", "dxc, dt,", "fine patches stepped at the coarse spacing"),
 ]
 
 
 def _run_mutant(case):
     fname, text, repl, what = case
+    if fname == AMR:
+        return _run_python_mutant(case)
     with tempfile.TemporaryDirectory() as tmp:
         for f in (FWD, ADJ, MHD):
             shutil.copy(os.path.join(ORACLE, f), tmp)
@@ -81,6 +103,23 @@ def _run_mutant(case):
         if build.returncode != 0:
             return what, "mutant does not compile: " + build.stderr[-300:]
         env["ORACLE_LIB_DIR"] = tmp
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", PINS[fname])],
+                           cwd=ROOT, env=env, capture_output=True, text=True)
+        return what, ("caught" if r.returncode != 0 else "NOT CAUGHT")
+
+
+def _run_python_mutant(case):
+    """The AMR oracle is Python: the pins load a mutated copy of it named by
+    ORACLE_AMR_FILE, on top of the repository's own compiled oracle."""
+    fname, text, repl, what = case
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, fname)
+        src = open(os.path.join(ORACLE, fname)).read()
+        if src.count(text) != 1:
+            return what, "pattern not found exactly once"
+        open(path, "w").write(src.replace(text, repl))
+        env = dict(os.environ, OMP_NUM_THREADS="2", ORACLE_AMR_FILE=path)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", PINS[fname])],
                            cwd=ROOT, env=env, capture_output=True, text=True)
