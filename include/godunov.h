@@ -272,6 +272,78 @@ int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const v
                double gamma, double dx, double cfl, double *dt_dev, double *ch_dev,
                void *hip_stream);
 
+/* ------------------------------------------------------------ two-level AMR
+ *
+ * The seams of one step of a two-level hierarchy around the batched step
+ * (Sec. 3: the GPU receives patches of inner cells together with boundary
+ * cells taken from the neighbouring grids; Sec. 4: the step returns the
+ * boundary fluxes that flux correction between levels needs). The coarse
+ * level is a periodic box of ncx x ncy x ncz cells of width dx_coarse
+ * (layout [5][ncz][ncy][ncx]); the fine level is a set of disjoint patches
+ * refined by 2, each covering whole coarse cells strictly inside the box
+ * (no patch crosses the periodic boundary), stored as a batch with ng = 2
+ * (gd_patch layouts, fine cell width dx_coarse / 2). One step, with the same
+ * dt on both levels:
+ *   1. ghost fill: every ghost cell of a fine patch (both layers, corners
+ *      included) takes the fine cell at the same place if a fine patch covers
+ *      it, else the coarse cell containing it (piecewise-constant
+ *      prolongation); positions wrap periodically;
+ *   2. the coarse box and the fine patches each take one step (the fine
+ *      batch with its boundary fluxes);
+ *   3. refluxing: an uncovered coarse cell next to a fine patch had the
+ *      coarse flux F_c through the shared face in its update; the mean
+ *      <F_f> of the four fine fluxes through that face replaces it:
+ *      U += dt/dx_c (<F_f> - F_c) if the face is the cell's lower face along
+ *      d, U += dt/dx_c (F_c - <F_f>) if it is its upper face. F_c is
+ *      recomputed from the old coarse state with the step's own arithmetic;
+ *      a cell's faces are applied one after another in a fixed order;
+ *   4. averaging down: each covered coarse cell becomes the mean of its eight
+ *      children, ((c000 + c100) + (c010 + c110)) + ((c001 + c101) + (c011 +
+ *      c111)) times 1/8, x fastest.
+ * The composite state (uncovered coarse cells and every fine cell) is then
+ * conserved to rounding. */
+typedef struct gd_amr gd_amr;
+
+typedef struct {
+    int32_t lo[3];          /* coarse cell (x, y, z) of the patch's lower corner */
+    int32_t n[3];           /* interior extents in fine cells (nx, ny, nz): even, >= 2 */
+    int64_t u_in_off, u_out_off, flux_off;   /* as in gd_patch; flux_off >= 0 */
+} gd_amr_patch;
+
+/* Build the device tables of a hierarchy on ctx's device (the only
+ * allocation of the AMR calls; synchronises the device). patches is a HOST
+ * array of npatch >= 0 entries: lo >= 0 and lo + n/2 <= nc on every axis,
+ * patches disjoint, 2 nc <= 16384 per axis, ncx ncy ncz < 2^31. Violations
+ * return GD_E_ARG with *plan = NULL. The plan belongs to ctx's device and
+ * stays valid until gd_amr_destroy. */
+int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int npatch,
+                  const gd_amr_patch *patches, gd_amr **plan);
+int gd_amr_destroy(gd_amr *plan);
+
+/* Step 1: write every ghost cell of every fine patch in fine_in_base from
+ * the interiors of the fine patches and from coarse_u. Interior cells are
+ * not written. dtype is a gd_dtype. */
+int gd_amr_fill_ghosts(gd_ctx *ctx, const gd_amr *plan, int dtype, const void *coarse_u,
+                       void *fine_in_base, void *hip_stream);
+
+/* Steps 3 and 4 in one launch: coarse_new (the coarse box after its step)
+ * is refluxed with fine_flux_base and its covered cells are averaged down
+ * from fine_out_base. coarse_old is the coarse state the step started from
+ * (F_c is recomputed from it), with opts' limiter, Riemann solver and floors
+ * (opts->bc is ignored). dt from the host, or from *dt_dev when not NULL. */
+int gd_amr_reflux(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_old,
+                  void *coarse_new, const void *fine_out_base, const void *fine_flux_base,
+                  double gamma, double dt, const double *dt_dev, void *hip_stream);
+
+/* Steps 1-4: ghost fill, coarse step (coarse_in -> coarse_out), batched
+ * fine step (fine_in_base -> fine_out_base with fluxes into fine_flux_base),
+ * refluxing and averaging down into coarse_out; five launches on
+ * hip_stream. A host dt is first stored in a device scalar of the plan, so
+ * two calls with one plan in flight on different streams race. */
+int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_in,
+                void *coarse_out, void *fine_in_base, void *fine_out_base, void *fine_flux_base,
+                double gamma, double dt, const double *dt_dev, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

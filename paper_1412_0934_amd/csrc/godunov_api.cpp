@@ -798,3 +798,321 @@ int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const v
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ two-level AMR
+
+struct gd_amr {
+    int device = 0;
+    int nc[3] = { 0, 0, 0 };
+    double dx = 0.0;
+    std::vector<gd_patch> fine;     // descriptors of the fine batch (ng 2, dx / 2)
+    int64_t in_end = 0, out_end = 0, fl_end = 0;   // fine buffer extents, elements
+    void *mem = nullptr;            // one device block holding every table
+    double *d_dt = nullptr;         // dt of gd_amr_step when given on the host
+    gd::AmrTables t{};
+};
+
+namespace {
+
+int64_t coarse_elems(const gd_amr *a) { return 5LL * a->nc[0] * a->nc[1] * a->nc[2]; }
+
+int check_plan(gd_ctx *ctx, const gd_amr *plan)
+{
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if (!plan) return fail(ctx, GD_E_ARG, "plan is NULL");
+    if (plan->device != ctx->device)
+        return fail(ctx, GD_E_ARG, "plan was built on device %d, ctx is on device %d", plan->device,
+                    ctx->device);
+    return GD_OK;
+}
+
+int amr_fill_impl(gd_ctx *ctx, const gd_amr *plan, int dtype, const void *coarse_u,
+                  void *fine_in_base, hipStream_t s)
+{
+    int r;
+    if ((r = check_plan(ctx, plan))) return r;
+    if (dtype != GD_F64 && dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", dtype);
+    if (!coarse_u || (!fine_in_base && plan->t.nfill)) return fail(ctx, GD_E_ARG, "NULL state pointer");
+    const size_t es = dtype == GD_F32 ? 4 : 8;
+    if (fine_in_base && overlap(coarse_u, coarse_elems(plan) * es, fine_in_base, plan->in_end * es))
+        return fail(ctx, GD_E_ARG, "fine_in_base range overlaps coarse_u");
+    if ((r = set_device(ctx))) return r;
+    int e = gd::launch_amr_fill(dtype, plan->t, coarse_u, fine_in_base, s);
+    if (e) return hip_fail(ctx, e, "gd_amr_fill_ghosts launch");
+    return GD_OK;
+}
+
+int amr_seam_impl(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_old,
+                  void *coarse_new, const void *fine_out, const void *fine_flux, double gamma,
+                  double dt, const double *dt_dev, hipStream_t s)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if ((r = check_plan(ctx, plan))) return r;
+    if ((r = check_scalars(ctx, gamma, plan->dx, dt_dev ? 0.0 : dt))) return r;
+    const bool fine = !plan->fine.empty();
+    if (!coarse_old || !coarse_new || (fine && (!fine_out || !fine_flux)))
+        return fail(ctx, GD_E_ARG, "NULL state pointer");
+    const size_t es = elem_size(opts), nc = coarse_elems(plan) * es;
+    if (overlap(coarse_old, nc, coarse_new, nc)) return fail(ctx, GD_E_ARG, "coarse_new overlaps coarse_old");
+    if (fine && (overlap(coarse_new, nc, fine_out, plan->out_end * es) ||
+                 overlap(coarse_new, nc, fine_flux, plan->fl_end * es)))
+        return fail(ctx, GD_E_ARG, "coarse_new overlaps a fine buffer");
+    if ((r = set_device(ctx))) return r;
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    int e = gd::launch_amr_seam(opts->dtype, opts->limiter, opts->riemann, plan->t, coarse_old,
+                                coarse_new, fine_out, fine_flux, sc, plan->dx, dt, dt_dev, s);
+    if (e) return hip_fail(ctx, e, "gd_amr_reflux launch");
+    return GD_OK;
+}
+
+// Device block layout: each table at a 256-byte aligned offset.
+struct Block {
+    size_t size = 0;
+    size_t add(size_t bytes)
+    {
+        size_t at = size;
+        size += (bytes + 255) / 256 * 256;
+        return at;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int npatch,
+                  const gd_amr_patch *patches, gd_amr **plan)
+{
+    if (!plan) return fail(ctx, GD_E_ARG, "plan pointer is NULL");
+    *plan = nullptr;
+    const int nc[3] = { ncx, ncy, ncz };
+    for (int a = 0; a < 3; ++a)
+        if (nc[a] < 1 || nc[a] > 8192) return fail(ctx, GD_E_ARG, "coarse extents must be in [1, 8192]");
+    const int64_t ncell = (int64_t)ncx * ncy * ncz;
+    if (ncell >= 0x7fffffffLL) return fail(ctx, GD_E_ARG, "coarse box has 2^31 cells or more");
+    if (!(dx_coarse > 0.0)) return fail(ctx, GD_E_ARG, "dx_coarse must be > 0");
+    if (npatch < 0 || (npatch > 0 && !patches)) return fail(ctx, GD_E_ARG, "bad patch list");
+
+    std::vector<int32_t> owner(ncell, -1);
+    auto cidx = [&](int x, int y, int z) { return ((int64_t)z * ncy + y) * ncx + x; };
+    std::vector<gd::AmrPatch> dp(npatch);
+    std::vector<gd_patch> fine(npatch);
+    int64_t in_end = 0, out_end = 0, fl_end = 0;
+    for (int p = 0; p < npatch; ++p) {
+        const gd_amr_patch &P = patches[p];
+        for (int a = 0; a < 3; ++a) {
+            if (P.n[a] < 2 || P.n[a] % 2) return fail(ctx, GD_E_ARG, "patch %d: extents must be even and >= 2", p);
+            if (P.lo[a] < 0 || P.lo[a] + P.n[a] / 2 > nc[a])
+                return fail(ctx, GD_E_ARG, "patch %d: not inside the coarse box", p);
+        }
+        if (P.u_in_off < 0 || P.u_out_off < 0 || P.flux_off < 0)
+            return fail(ctx, GD_E_ARG, "patch %d: negative offset", p);
+        if ((int64_t)(P.n[0] + 4) * (P.n[1] + 4) * (P.n[2] + 4) >= 0x7fffffffLL)
+            return fail(ctx, GD_E_ARG, "patch %d: too large", p);
+        for (int z = P.lo[2]; z < P.lo[2] + P.n[2] / 2; ++z)
+            for (int y = P.lo[1]; y < P.lo[1] + P.n[1] / 2; ++y)
+                for (int x = P.lo[0]; x < P.lo[0] + P.n[0] / 2; ++x) {
+                    int32_t &o = owner[cidx(x, y, z)];
+                    if (o >= 0) return fail(ctx, GD_E_ARG, "patches %d and %d overlap", o, p);
+                    o = p;
+                }
+        gd::AmrPatch &d = dp[p];
+        for (int a = 0; a < 3; ++a) { d.lo[a] = P.lo[a]; d.n[a] = P.n[a]; }
+        d.in_off = P.u_in_off; d.out_off = P.u_out_off; d.flux_off = P.flux_off;
+        gd_patch &f = fine[p];
+        f.nx = P.n[0]; f.ny = P.n[1]; f.nz = P.n[2]; f.ng = 2;
+        f.u_in_off = P.u_in_off; f.u_out_off = P.u_out_off; f.flux_off = P.flux_off;
+        f.dx = dx_coarse / 2; f.dt = 0.0;
+        in_end = std::max<int64_t>(in_end, P.u_in_off + in_elems(P.n[0], P.n[1], P.n[2], 2, false));
+        out_end = std::max<int64_t>(out_end, P.u_out_off + 5LL * P.n[0] * P.n[1] * P.n[2]);
+        fl_end = std::max<int64_t>(fl_end, P.flux_off + flux_elems(P.n[0], P.n[1], P.n[2]));
+    }
+
+    // ghost fill: 256-cell pieces of each ghosted box
+    std::vector<gd::AmrFillItem> fill;
+    for (int p = 0; p < npatch; ++p) {
+        const int box = (dp[p].n[0] + 4) * (dp[p].n[1] + 4) * (dp[p].n[2] + 4);
+        for (int s0 = 0; s0 < box; s0 += 256) fill.push_back(gd::AmrFillItem{ p, s0 });
+    }
+    // interface faces, per patch, axis, side and footprint cell; grouped by
+    // the uncovered cell they correct, in that order
+    std::vector<int32_t> cells;
+    std::vector<std::vector<gd::AmrFace>> per_cell;
+    std::vector<int32_t> slot(ncell, -1);
+    for (int p = 0; p < npatch; ++p) {
+        const gd::AmrPatch &P = dp[p];
+        const int size[3] = { P.n[0] / 2, P.n[1] / 2, P.n[2] / 2 };
+        const int64_t sx = 5LL * P.n[2] * P.n[1], sy = 5LL * P.n[2] * P.n[0], sz = 5LL * P.n[1] * P.n[0];
+        const int64_t sheet0[6] = { 0, sx, 2 * sx, 2 * sx + sy, 2 * sx + 2 * sy, 2 * sx + 2 * sy + sz };
+        for (int d = 0; d < 3; ++d) {
+            const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+            for (int side = 0; side < 2; ++side)
+                for (int b = 0; b < size[t2]; ++b)
+                    for (int a = 0; a < size[t1]; ++a) {
+                        int c[3] = { P.lo[0], P.lo[1], P.lo[2] };
+                        c[t1] += a;
+                        c[t2] += b;
+                        c[d] = P.lo[d] + (side ? size[d] - 1 : 0);
+                        int o[3] = { c[0], c[1], c[2] };
+                        o[d] = (c[d] + (side ? 1 : -1) + nc[d]) % nc[d];
+                        const int64_t oi = cidx(o[0], o[1], o[2]);
+                        if (owner[oi] >= 0) continue;
+                        gd::AmrFace f{};
+                        const int *rc = side ? o : c;
+                        f.right = (int32_t)cidx(rc[0], rc[1], rc[2]);
+                        f.dside = 2 * d + side;
+                        // sheet axes (slow, fast): x (z, y), y (z, x), z (y, x)
+                        const int slow = d == 2 ? 1 : 2, fast = d == 0 ? 1 : 0;
+                        const int ls = 2 * (c[slow] - P.lo[slow]), lf = 2 * (c[fast] - P.lo[fast]);
+                        f.row = P.n[fast];
+                        f.vstride = (int32_t)((d == 0 ? sx : (d == 1 ? sy : sz)) / 5);
+                        f.fine = P.flux_off + sheet0[2 * d + side] + (int64_t)ls * f.row + lf;
+                        if (slot[oi] < 0) {
+                            slot[oi] = (int32_t)cells.size();
+                            cells.push_back((int32_t)oi);
+                            per_cell.emplace_back();
+                        }
+                        per_cell[slot[oi]].push_back(f);
+                    }
+        }
+    }
+    std::vector<int32_t> start(1, 0);
+    std::vector<gd::AmrFace> faces;
+    for (auto &v : per_cell) {
+        faces.insert(faces.end(), v.begin(), v.end());
+        start.push_back((int32_t)faces.size());
+    }
+    std::vector<gd::AmrCover> cover;
+    for (int p = 0; p < npatch; ++p) {
+        const gd::AmrPatch &P = dp[p];
+        for (int k = 0; k < P.n[2] / 2; ++k)
+            for (int j = 0; j < P.n[1] / 2; ++j)
+                for (int i = 0; i < P.n[0] / 2; ++i) {
+                    gd::AmrCover c{};
+                    c.coarse = (int32_t)cidx(P.lo[0] + i, P.lo[1] + j, P.lo[2] + k);
+                    c.patch = p;
+                    c.child = P.out_off + ((int64_t)2 * k * P.n[1] + 2 * j) * P.n[0] + 2 * i;
+                    cover.push_back(c);
+                }
+    }
+    if (fill.size() > 0x7fffffff / 2 || cells.size() + cover.size() > 0x7fffffff / 2)
+        return fail(ctx, GD_E_ARG, "hierarchy too large");
+
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    int r;
+    if ((r = set_device(ctx))) return r;
+    Block blk;
+    const size_t o_owner = blk.add(owner.size() * 4), o_patch = blk.add(dp.size() * sizeof(gd::AmrPatch));
+    const size_t o_fill = blk.add(fill.size() * sizeof(gd::AmrFillItem));
+    const size_t o_cells = blk.add(cells.size() * 4), o_start = blk.add(start.size() * 4);
+    const size_t o_faces = blk.add(faces.size() * sizeof(gd::AmrFace));
+    const size_t o_cover = blk.add(cover.size() * sizeof(gd::AmrCover));
+    const size_t o_dt = blk.add(sizeof(double));
+    gd_amr *a = new gd_amr();
+    a->device = ctx->device;
+    for (int k = 0; k < 3; ++k) a->nc[k] = nc[k];
+    a->dx = dx_coarse;
+    a->fine = fine;
+    a->in_end = in_end; a->out_end = out_end; a->fl_end = fl_end;
+    hipError_t e = hipMalloc(&a->mem, blk.size);
+    if (e != hipSuccess) {
+        delete a;
+        return fail(ctx, GD_E_NOMEM, "hipMalloc of %zu bytes for the AMR tables failed", blk.size);
+    }
+    char *base = (char *)a->mem;
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    put(o_owner, owner.data(), owner.size() * 4);
+    put(o_patch, dp.data(), dp.size() * sizeof(gd::AmrPatch));
+    put(o_fill, fill.data(), fill.size() * sizeof(gd::AmrFillItem));
+    put(o_cells, cells.data(), cells.size() * 4);
+    put(o_start, start.data(), start.size() * 4);
+    put(o_faces, faces.data(), faces.size() * sizeof(gd::AmrFace));
+    put(o_cover, cover.data(), cover.size() * sizeof(gd::AmrCover));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(a->mem);
+        delete a;
+        return hip_fail(ctx, e, "upload of the AMR tables");
+    }
+    gd::AmrTables &t = a->t;
+    for (int k = 0; k < 3; ++k) t.nc[k] = nc[k];
+    t.nfill = (int32_t)fill.size();
+    t.ncells = (int32_t)cells.size();
+    t.ncover = (int32_t)cover.size();
+    t.owner = (const int32_t *)(base + o_owner);
+    t.patches = (const gd::AmrPatch *)(base + o_patch);
+    t.fill = (const gd::AmrFillItem *)(base + o_fill);
+    t.cells = (const int32_t *)(base + o_cells);
+    t.cell_start = (const int32_t *)(base + o_start);
+    t.faces = (const gd::AmrFace *)(base + o_faces);
+    t.cover = (const gd::AmrCover *)(base + o_cover);
+    a->d_dt = (double *)(base + o_dt);
+    *plan = a;
+    return GD_OK;
+}
+
+int gd_amr_destroy(gd_amr *plan)
+{
+    if (!plan) return GD_OK;
+    (void)hipSetDevice(plan->device);
+    if (plan->mem) (void)hipFree(plan->mem);
+    delete plan;
+    return GD_OK;
+}
+
+int gd_amr_fill_ghosts(gd_ctx *ctx, const gd_amr *plan, int dtype, const void *coarse_u,
+                       void *fine_in_base, void *hip_stream)
+{
+    return amr_fill_impl(ctx, plan, dtype, coarse_u, fine_in_base, (hipStream_t)hip_stream);
+}
+
+int gd_amr_reflux(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_old,
+                  void *coarse_new, const void *fine_out_base, const void *fine_flux_base,
+                  double gamma, double dt, const double *dt_dev, void *hip_stream)
+{
+    return amr_seam_impl(ctx, plan, opts, coarse_old, coarse_new, fine_out_base, fine_flux_base,
+                         gamma, dt, dt_dev, (hipStream_t)hip_stream);
+}
+
+int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_in,
+                void *coarse_out, void *fine_in_base, void *fine_out_base, void *fine_flux_base,
+                double gamma, double dt, const double *dt_dev, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if ((r = check_plan(ctx, plan))) return r;
+    if ((r = check_scalars(ctx, gamma, plan->dx, dt_dev ? 0.0 : dt))) return r;
+    const bool fine = !plan->fine.empty();
+    if (!coarse_in || !coarse_out || (fine && (!fine_in_base || !fine_out_base || !fine_flux_base)))
+        return fail(ctx, GD_E_ARG, "NULL state pointer");
+    const size_t es = elem_size(opts), nc = coarse_elems(plan) * es;
+    if (fine && (overlap(coarse_in, nc, fine_in_base, plan->in_end * es) ||
+                 overlap(coarse_out, nc, fine_in_base, plan->in_end * es)))
+        return fail(ctx, GD_E_ARG, "fine_in_base overlaps a coarse buffer");
+    if ((r = set_device(ctx))) return r;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double *dtp = dt_dev;
+    if (!dtp) {
+        int e = gd::launch_set_scalar(plan->d_dt, dt, s);
+        if (e) return hip_fail(ctx, e, "gd_amr_step dt store");
+        dtp = plan->d_dt;
+    }
+    gd_opts o = *opts;
+    if (fine && (r = amr_fill_impl(ctx, plan, o.dtype, coarse_in, fine_in_base, s))) return r;
+    o.bc = GD_PERIODIC;
+    if ((r = step_impl(ctx, &o, plan->nc[0], plan->nc[1], plan->nc[2], 0, coarse_in, coarse_out,
+                       nullptr, gamma, plan->dx, 0.0, dtp, 0.0, nullptr, s)))
+        return r;
+    o.bc = GD_GHOSTED;
+    if (fine && (r = step_batched_impl(ctx, &o, (int)plan->fine.size(), plan->fine.data(),
+                                       fine_in_base, fine_out_base, fine_flux_base, dtp, gamma,
+                                       0.0, nullptr, s)))
+        return r;
+    return amr_seam_impl(ctx, plan, &o, coarse_in, coarse_out, fine_out_base, fine_flux_base,
+                         gamma, 0.0, dtp, s);
+}
+
+}  // extern "C"

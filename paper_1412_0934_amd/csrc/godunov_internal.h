@@ -112,4 +112,59 @@ int launch_mhd_speeds(int dtype, int nx, int ny, int nz, const void *u, const Mh
                       double cfl, double *dt_dev, double *ch_dev, unsigned long long *acc,
                       hipStream_t s);
 
+// Two-level AMR seams (godunov_amr.hip). Tables are built on the host once
+// per hierarchy; coarse cells are indexed (z * ny + y) * nx + x.
+struct AmrPatch {
+    int32_t lo[3];          // coarse cell (x, y, z) of the lower corner
+    int32_t n[3];           // interior extents in fine cells (even)
+    int64_t in_off, out_off, flux_off;
+};
+
+// 256 consecutive cells of one patch's ghosted box, for the ghost fill.
+struct AmrFillItem {
+    int32_t patch, start;
+};
+
+// One coarse-fine face. right: coarse cell on the + side of the face;
+// dside = 2 d + side, side 1 when the uncovered cell is on the + side;
+// fine: element offset in the flux buffer of variable 0 of the first of the
+// 2x2 fine faces; row: elements between the two rows of the block; vstride:
+// elements between variables of the sheet.
+struct AmrFace {
+    int32_t right, dside;
+    int64_t fine;
+    int32_t row, vstride;
+};
+
+// A covered coarse cell and the offset in the fine output of variable 0 of
+// its child at (0, 0, 0).
+struct AmrCover {
+    int32_t coarse, patch;
+    int64_t child;
+};
+
+struct AmrTables {
+    int32_t nc[3];
+    int32_t nfill, ncells, ncover;
+    const int32_t *owner;           // coarse cell -> covering patch or -1
+    const AmrPatch *patches;
+    const AmrFillItem *fill;
+    const int32_t *cells;           // uncovered coarse cells with interface faces
+    const int32_t *cell_start;      // ncells + 1 offsets into faces
+    const AmrFace *faces;
+    const AmrCover *cover;
+};
+
+int launch_amr_fill(int dtype, const AmrTables &t, const void *coarse, void *fine, hipStream_t s);
+
+// Refluxing of the uncovered cells and averaging down of the covered ones,
+// one launch; dt_dev, when not null, replaces dt.
+int launch_amr_seam(int dtype, int limiter, int riemann, const AmrTables &t, const void *coarse_old,
+                    void *coarse_new, const void *fine_out, const void *fine_flux,
+                    const Scalars &sc, double dx_coarse, double dt, const double *dt_dev,
+                    hipStream_t s);
+
+// *dst = v, stream-ordered (capturable, unlike a host-to-device copy).
+int launch_set_scalar(double *dst, double v, hipStream_t s);
+
 }  // namespace gd

@@ -12,6 +12,8 @@ Entry points (same names as the C ABI, see include/godunov.h):
     cfl_dt(u, gamma, dx, cfl)         CFL time step as a device scalar
     step_mhd(u, gamma, dx, dt, ch)    ideal-MHD step (HLLD + GLM) of a periodic box
     cfl_dt_mhd(u, gamma, dx, cfl)     its time step and cleaning speed
+    AmrPlan(nc, dx_coarse, table)     two-level hierarchy: ghost fill, refluxing,
+                                      averaging down, the whole two-level step
     GodunovRollout                    torch.autograd.Function over K steps
                                       with checkpointed recomputation
 """
@@ -59,11 +61,23 @@ PATCH_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("ng", "<i4
                         ("dx", "<f8"), ("dt", "<f8")], align=True)
 assert PATCH_DTYPE.itemsize == ctypes.sizeof(gd_patch)
 
+
+class gd_amr_patch(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("n", ctypes.c_int32 * 3),
+                ("u_in_off", ctypes.c_int64), ("u_out_off", ctypes.c_int64),
+                ("flux_off", ctypes.c_int64)]
+
+
+AMR_PATCH_DTYPE = np.dtype([("lo", "<i4", (3,)), ("n", "<i4", (3,)), ("u_in_off", "<i8"),
+                            ("u_out_off", "<i8"), ("flux_off", "<i8")], align=True)
+assert AMR_PATCH_DTYPE.itemsize == ctypes.sizeof(gd_amr_patch)
+
 EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset_stats",
            "godunov_step", "godunov_step_batched", "godunov_step_adjoint", "cfl_dt",
            "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
            "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "godunov_step_mhd_cfl",
-           "cfl_dt_mhd")
+           "cfl_dt_mhd", "gd_amr_create", "gd_amr_destroy", "gd_amr_fill_ghosts", "gd_amr_reflux",
+           "gd_amr_step")
 
 _lib = None
 _lock = threading.Lock()
@@ -107,6 +121,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.cfl_dt_mhd.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, dbl, dbl, dbl, vp, vp, vp]
         lib.godunov_step_mhd_cfl.argtypes = [vp, P(gd_opts), i32, i32, i32, vp, vp, dbl, dbl, dbl,
                                              vp, dbl, vp, dbl, dbl, vp, vp, vp]
+        lib.gd_amr_create.argtypes = [vp, i32, i32, i32, dbl, i32, vp, P(vp)]
+        lib.gd_amr_destroy.argtypes = [vp]
+        lib.gd_amr_fill_ghosts.argtypes = [vp, vp, i32, vp, vp, vp]
+        lib.gd_amr_reflux.argtypes = [vp, vp, P(gd_opts), vp, vp, vp, vp, dbl, dbl, vp, vp]
+        lib.gd_amr_step.argtypes = [vp, vp, P(gd_opts), vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -480,3 +499,105 @@ def cfl_dt_mhd(u, gamma, dx, cfl=0.4, *, out_dt=None, out_ch=None, rho_floor=RHO
                                  float(dx), float(cfl), _ptr(out_dt), _ptr(out_ch),
                                  _stream(stream)))
     return out_dt, out_ch
+
+
+# ------------------------------------------------------------ two-level AMR
+
+def amr_patch_table(lo, n, u_in_off, u_out_off, flux_off) -> np.ndarray:
+    """Structured array of gd_amr_patch records: lo (P, 3) coarse cells
+    (x, y, z), n (P, 3) fine interior extents (nx, ny, nz)."""
+    lo = np.asarray(lo).reshape(-1, 3)
+    t = np.zeros(len(lo), dtype=AMR_PATCH_DTYPE)
+    t["lo"], t["n"] = lo, np.asarray(n).reshape(-1, 3)
+    t["u_in_off"], t["u_out_off"], t["flux_off"] = u_in_off, u_out_off, flux_off
+    return t
+
+
+class AmrPlan:
+    """A gd_amr: the device tables of a periodic coarse box of nc = (ncx, ncy,
+    ncz) cells of width dx_coarse and fine patches refined by 2 (see
+    amr_patch_table; fine buffers in the batched layout with ng = 2)."""
+
+    def __init__(self, nc, dx_coarse, table, device=None):
+        self.ctx = context(device)
+        self.nc = tuple(int(v) for v in nc)
+        self.dx_coarse = float(dx_coarse)
+        self.table = np.ascontiguousarray(table, dtype=AMR_PATCH_DTYPE)
+        n = self.table["n"].astype(np.int64)
+        if len(n):
+            self.in_end = int((self.table["u_in_off"] + 5 * np.prod(n + 4, axis=1)).max())
+            self.out_end = int((self.table["u_out_off"] + 5 * np.prod(n, axis=1)).max())
+            self.flux_end = int((self.table["flux_off"] + 10 * (n[:, 2] * n[:, 1] + n[:, 2] * n[:, 0]
+                                                                + n[:, 1] * n[:, 0])).max())
+        else:
+            self.in_end = self.out_end = self.flux_end = 0
+        h = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.gd_amr_create(self.ctx.handle, *self.nc, self.dx_coarse,
+                                                  len(self.table), self.table.ctypes.data,
+                                                  ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and self.handle.value:
+                self.ctx.lib.gd_amr_destroy(self.handle)
+        except Exception:
+            pass
+
+    def _check(self, coarse=(), fine_in=None, fine_out=None, fine_flux=None):
+        for name, t in coarse:
+            _check_tensor(t, name)
+            if t.numel() != 5 * self.nc[0] * self.nc[1] * self.nc[2]:
+                raise ValueError(f"{name} must hold 5 x {self.nc} values")
+        for name, t, need in (("fine_in", fine_in, self.in_end), ("fine_out", fine_out, self.out_end),
+                              ("fine_flux", fine_flux, self.flux_end)):
+            if t is not None:
+                _check_tensor(t, name)
+                if t.numel() < need:
+                    raise ValueError(f"{name} holds {t.numel()} values, the patches need {need}")
+
+    def fill_ghosts(self, coarse, fine_in, stream=None):
+        """Write every ghost cell of the fine patches in fine_in."""
+        self._check([("coarse", coarse)], fine_in=fine_in)
+        _check_tensor(fine_in, "fine_in", coarse.dtype)
+        self.ctx.check(self.ctx.lib.gd_amr_fill_ghosts(
+            self.ctx.handle, self.handle, DTYPES[coarse.dtype], _ptr(coarse), _ptr(fine_in),
+            _stream(stream)))
+        return fine_in
+
+    def reflux(self, coarse_old, coarse_new, fine_out, fine_flux, gamma, dt=None, *, dt_dev=None,
+               limiter="minmod", riemann="hllc", rho_floor=RHO_FLOOR, p_floor=P_FLOOR,
+               stream=None):
+        """Refluxing and averaging down into coarse_new, in place."""
+        self._check([("coarse_old", coarse_old), ("coarse_new", coarse_new)], fine_out=fine_out,
+                    fine_flux=fine_flux)
+        if dt_dev is not None:
+            _check_tensor(dt_dev, "dt_dev", torch.float64)
+        o = _opts(coarse_old.dtype, True, limiter, riemann, rho_floor, p_floor)
+        self.ctx.check(self.ctx.lib.gd_amr_reflux(
+            self.ctx.handle, self.handle, ctypes.byref(o), _ptr(coarse_old), _ptr(coarse_new),
+            _ptr(fine_out), _ptr(fine_flux), float(gamma), float(dt or 0.0), _ptr(dt_dev),
+            _stream(stream)))
+        return coarse_new
+
+    def step(self, coarse_in, fine_in, gamma, dt=None, *, coarse_out, fine_out, fine_flux,
+             dt_dev=None, limiter="minmod", riemann="hllc", rho_floor=RHO_FLOOR, p_floor=P_FLOOR,
+             stream=None):
+        """One two-level step: ghost fill (into fine_in), coarse and fine
+        steps, refluxing and averaging down into coarse_out."""
+        self._check([("coarse_in", coarse_in), ("coarse_out", coarse_out)], fine_in=fine_in,
+                    fine_out=fine_out, fine_flux=fine_flux)
+        for name, t in (("fine_in", fine_in), ("fine_out", fine_out), ("fine_flux", fine_flux),
+                        ("coarse_out", coarse_out)):
+            if t.dtype != coarse_in.dtype:
+                raise TypeError(f"{name} must have dtype {coarse_in.dtype}")
+        if dt_dev is not None:
+            _check_tensor(dt_dev, "dt_dev", torch.float64)
+        elif dt is None:
+            raise ValueError("give dt or dt_dev")
+        o = _opts(coarse_in.dtype, True, limiter, riemann, rho_floor, p_floor)
+        self.ctx.check(self.ctx.lib.gd_amr_step(
+            self.ctx.handle, self.handle, ctypes.byref(o), _ptr(coarse_in), _ptr(coarse_out),
+            _ptr(fine_in), _ptr(fine_out), _ptr(fine_flux), float(gamma), float(dt or 0.0),
+            _ptr(dt_dev), _stream(stream)))
+        return coarse_out, fine_out, fine_flux

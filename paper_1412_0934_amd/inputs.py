@@ -224,6 +224,8 @@ def batch_layout(dims, ng, dx, order_seed=None):
 
     def offsets(sizes):
         off = np.zeros(npatch, dtype=np.int64)
+        if npatch == 0:
+            return off, 0
         ordered = sizes[place]
         off[place] = np.concatenate([[0], np.cumsum(ordered)[:-1]])
         return off, int(sizes.sum())
@@ -424,17 +426,22 @@ def _smooth_state(rng, gamma):
     return at
 
 
-def amr_hierarchy(nc=32, nfine=8, seed=11, gamma=GAMMA, max_size=5, touch=0.5):
+def amr_hierarchy(nc=32, nfine=8, seed=11, gamma=GAMMA, max_size=5, touch=0.5, boxes=None):
     """Seeded two-level hierarchy: the same smooth analytic state sampled at
     the coarse cell centres and at the fine cell centres of each patch.
     Patches are random boxes of 2..max_size coarse cells per axis, disjoint,
     inside [2, nc - 2) (no periodic crossing); with probability `touch` a new
-    patch is placed against an existing one, so fine-fine faces occur."""
+    patch is placed against an existing one, so fine-fine faces occur.
+    boxes, a list of (lo, size) in coarse cells, replaces the random ones."""
     rng = np.random.default_rng(seed)
     at = _smooth_state(rng, gamma)
     owner = -np.ones((nc, nc, nc), dtype=np.int64)          # [x][y][z]
     los, sizes = [], []
     tries = 0
+    if boxes is not None:
+        los = [np.asarray(b[0], dtype=np.int64) for b in boxes]
+        sizes = [np.asarray(b[1], dtype=np.int64) for b in boxes]
+        nfine = 0
     while len(los) < nfine and tries < 5000:
         tries += 1
         size = rng.integers(2, max_size + 1, size=3)

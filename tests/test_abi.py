@@ -153,3 +153,42 @@ def test_create_without_device_fails_cleanly(lib):
     r = lib.gd_create(ctypes.byref(h), 0)
     assert r == -2 and not h.value
     assert b"device" in lib.gd_last_error(None)
+
+
+def _amr_table(rows):
+    from paper_1412_0934_amd import godunov
+    lo = [r[0] for r in rows]
+    n = [r[1] for r in rows]
+    return godunov.amr_patch_table(lo, n, 0, 0, [r[2] if len(r) > 2 else 0 for r in rows])
+
+
+@pytest.mark.parametrize("case,rows,nc,msg", [
+    ("odd extent", [((2, 2, 2), (4, 3, 4))], 16, b"even"),
+    ("extent below 2", [((2, 2, 2), (0, 4, 4))], 16, b"even"),
+    ("outside the box", [((14, 2, 2), (6, 4, 4))], 16, b"inside"),
+    ("negative corner", [((-1, 2, 2), (4, 4, 4))], 16, b"inside"),
+    ("overlapping patches", [((2, 2, 2), (4, 4, 4)), ((3, 3, 3), (4, 4, 4))], 16, b"overlap"),
+    ("no flux sheets", [((2, 2, 2), (4, 4, 4), -1)], 16, b"negative"),
+    ("coarse box too large", [], 9000, b"coarse extents"),
+    ("valid, stops at the NULL context", [((2, 2, 2), (4, 4, 4)), ((4, 2, 2), (4, 4, 4))], 16,
+     b"ctx"),
+])
+def test_amr_create_validates_the_hierarchy(lib, case, rows, nc, msg):
+    t = _amr_table(rows)
+    plan = ctypes.c_void_p()
+    r = lib.gd_amr_create(None, nc, nc, nc, 1.0 / nc, len(t), t.ctypes.data if len(t) else None,
+                          ctypes.byref(plan))
+    assert r == -1, case
+    assert not plan.value
+    assert msg in lib.gd_last_error(None), lib.gd_last_error(None)
+
+
+def test_amr_calls_reject_a_null_plan(lib):
+    o = _opts(bc=1)
+    vp = ctypes.c_void_p
+    assert lib.gd_amr_fill_ghosts(None, None, 0, vp(16), vp(1 << 20), None) == -1
+    assert lib.gd_amr_reflux(None, None, ctypes.byref(o), vp(16), vp(1 << 20), vp(1 << 24),
+                             vp(1 << 28), 1.4, 0.01, None, None) == -1
+    assert lib.gd_amr_step(None, None, ctypes.byref(o), vp(16), vp(1 << 20), vp(1 << 24),
+                           vp(1 << 26), vp(1 << 28), 1.4, 0.01, None, None) == -1
+    assert lib.gd_amr_destroy(None) == 0
