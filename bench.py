@@ -45,7 +45,7 @@ METRIC = "Mcell-updates/s per Godunov step (plain vs batched), % HBM roofline; a
 # the step kernel's own code (its launch interface lives in godunov_internal.h,
 # whose other declarations do not change the kernel)
 KERNEL_SRC = [os.path.join(ROOT, "paper_1412_0934_amd", "csrc", f)
-              for f in ("godunov_kernels.hip", "godunov_math.h")]
+              for f in ("godunov_kernels.hip", "godunov_cell.h", "godunov_math.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_traffic.txt")
 
 
@@ -191,12 +191,77 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
                   + 4 * (d[:, 0] + d[:, 1] + d[:, 2])).sum()
     nbytes = es * (5 * read_cells + 5 * cells + batch.flux_size)
     gbs = nbytes / (ms * 1e-3) / 1e9
-    return {"workload": "4096 ghost-zoned patches 8^3..32^3 (p=.5/.3/.15/.05), ng=2, "
-                        "sine background + Mach-3 shock, minmod+HLLC, bflux returned",
-            "config": gd.get_config(dtype),
-            "dtype": dtype_name, "cells": int(cells), "ms_per_step": ms,
-            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
-            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    res = {"workload": "4096 ghost-zoned patches 8^3..32^3 (p=.5/.3/.15/.05), ng=2, "
+                       "sine background + Mach-3 shock, minmod+HLLC, bflux returned",
+           "config": gd.get_config(dtype),
+           "dtype": dtype_name, "cells": int(cells), "ms_per_step": ms,
+           "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
+           "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    if dtype == torch.float64:
+        res["plain"] = bench_plain(torch, gd, batch, u_in, out, flux, dt, cells, steps)
+    return res
+
+
+def bench_plain(torch, gd, batch, u_in, out, flux, dt, cells, steps):
+    """The same batch as 4096 separate godunov_step launches per step: issued
+    from the host one by one, and captured once into a HIP graph that is
+    replayed (the paper's per-patch GPU calls, against one persistent launch)."""
+    import ctypes
+    log("bench: plain per-patch launches (eager, then one captured graph)")
+    ctx = gd.context()
+    o = gd._opts(torch.float64, False, "minmod", "hllc", gd.RHO_FLOOR, gd.P_FLOOR)
+    es = 8
+    calls = []
+    for p in range(batch.npatch):
+        nx, ny, nz = (int(v) for v in batch.dims[p])
+        calls.append((nx, ny, nz, ctypes.c_void_p(u_in.data_ptr() + es * int(batch.u_in_off[p])),
+                      ctypes.c_void_p(out.data_ptr() + es * int(batch.u_out_off[p])),
+                      ctypes.c_void_p(flux.data_ptr() + es * int(batch.flux_off[p])),
+                      float(batch.dx[p])))
+    dtp = ctypes.c_void_p(dt.data_ptr())
+    lib, h, ob = ctx.lib, ctx.handle, ctypes.byref(o)
+
+    def issue(stream):
+        s = ctypes.c_void_p(stream.cuda_stream)
+        for nx, ny, nz, a, b, c, dx in calls:
+            r = lib.godunov_step(h, ob, nx, ny, nz, 2, a, b, c, GAMMA, dx, 0.0, dtp, s)
+            if r:
+                ctx.check(r)
+
+    stream = torch.cuda.current_stream()
+    issue(stream)
+    torch.cuda.synchronize()
+    n_eager = max(2, steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n_eager):
+        issue(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / n_eager
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        issue(side)                       # warm the capture stream once
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        issue(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    return {"launches_per_step": batch.npatch,
+            "eager_ms_per_step": round(eager_ms, 3),
+            "eager_mcell_per_s": cells / (eager_ms * 1e-3) / 1e6,
+            "graph_ms_per_step": round(graph_ms, 3),
+            "graph_mcell_per_s": cells / (graph_ms * 1e-3) / 1e6}
 
 
 bench_batched.cache = None
@@ -252,6 +317,76 @@ def bench_mhd(torch, gd, steps=10, warmup=2, n=128):
             "hbm_frac": 144 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "div_b_rms_start": div_b(u0), f"div_b_rms_after_{steps}_steps": div_b(last)}
 
+
+
+def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
+    """One two-level AMR step (gd_amr_step: ghost fill, periodic coarse step,
+    batched fine step with boundary fluxes, refluxing + averaging down) on a
+    periodic coarse box with fine patches refined by 2, all FP64; plus the
+    time of each stage from its own entry point, so the seams' share shows."""
+    import numpy as np
+    from paper_1412_0934_amd import inputs
+    log(f"bench: two-level AMR, {nc}^3 coarse + up to {nfine} fine patches")
+    h = inputs.amr_hierarchy(nc=nc, nfine=nfine, max_size=max_size, seed=21, gamma=GAMMA)
+    f = h.fine
+    table = gd.amr_patch_table(h.lo, h.n, f.u_in_off, f.u_out_off, f.flux_off)
+    plan = gd.AmrPlan((nc,) * 3, h.dx_coarse, table)
+    ci = torch.from_numpy(h.coarse).cuda()
+    co = torch.empty_like(ci)
+    fi = torch.from_numpy(np.nan_to_num(f.u_in)).cuda()
+    fo = torch.empty(f.u_out_size, dtype=torch.float64, device="cuda")
+    ff = torch.empty(f.flux_size, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.cfl_dt(ci, GAMMA, h.dx_coarse / 2, 0.5, periodic=True, out=dt)
+    fine_table = gd.patch_table(h.n, 2, f.u_in_off, f.u_out_off, f.flux_off, h.dx_coarse / 2, 0.0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.step(ci, fi, GAMMA, dt_dev=dt, coarse_out=co, fine_out=fo, fine_flux=ff)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # stage by stage, same work
+    stages = {"ghost_fill": lambda: plan.fill_ghosts(ci, fi),
+              "coarse_step": lambda: gd.step(ci, GAMMA, h.dx_coarse, dt_dev=dt, periodic=True,
+                                             out=co, want_bflux=False),
+              "fine_batched_step": lambda: gd.step_batched(fi, fine_table, GAMMA, out=fo, bflux=ff,
+                                                           dt_dev=dt),
+              "reflux_and_average": lambda: plan.reflux(ci, co, fo, ff, GAMMA, dt_dev=dt)}
+    stage_ms = {}
+    for name, fn in stages.items():
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        stage_ms[name] = round(a.elapsed_time(b) / steps, 4)
+    d = h.n.astype(np.int64)
+    fine_cells = int(np.prod(d, axis=1).sum())
+    ghosts = int((np.prod(d + 4, axis=1) - np.prod(d, axis=1)).sum())
+    cells = nc ** 3 + fine_cells
+    fill_bytes = 2 * 5 * 8 * ghosts
+    return {"workload": f"two-level AMR: periodic {nc}^3 coarse box + {len(h.lo)} disjoint fine "
+                        f"patches refined by 2 (2..{max_size} coarse cells per axis, {fine_cells} "
+                        "fine cells), smooth random Fourier state, minmod + HLLC, FP64, one "
+                        "gd_amr_step per step (5 launches, dt on the device)",
+            "patches": int(len(h.lo)), "coarse_cells": nc ** 3, "fine_cells": fine_cells,
+            "ghost_cells": ghosts, "ms_per_step": round(ms, 4),
+            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "stage_ms": stage_ms,
+            "seam_share": round((stage_ms["ghost_fill"] + stage_ms["reflux_and_average"]) /
+                                sum(stage_ms.values()), 4),
+            "ghost_fill_gbs": round(fill_bytes / (stage_ms["ghost_fill"] * 1e-3) / 1e9, 1)}
 
 def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
@@ -394,6 +529,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mhd", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -461,6 +597,8 @@ def main():
                            bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]
     if not args.no_mhd:
         also["mhd"] = bench_mhd(torch, gd)
+    if not args.no_amr:
+        also["amr"] = bench_amr(torch, gd)
     if not args.no_adjoint:
         also["adjoint"] = bench_adjoint(torch, gd)
     if also:

@@ -326,11 +326,14 @@ int gd_amr_destroy(gd_amr *plan);
 int gd_amr_fill_ghosts(gd_ctx *ctx, const gd_amr *plan, int dtype, const void *coarse_u,
                        void *fine_in_base, void *hip_stream);
 
-/* Steps 3 and 4 in one launch: coarse_new (the coarse box after its step)
+/* Steps 3 and 4 in two launches: coarse_new (the coarse box after its step)
  * is refluxed with fine_flux_base and its covered cells are averaged down
  * from fine_out_base. coarse_old is the coarse state the step started from
  * (F_c is recomputed from it), with opts' limiter, Riemann solver and floors
- * (opts->bc is ignored). dt from the host, or from *dt_dev when not NULL. */
+ * (opts->bc is ignored). dt from the host, or from *dt_dev when not NULL.
+ * The recomputed face states pass through scratch memory of the plan (80
+ * bytes per coarse-fine face, allocated by gd_amr_create), so two calls
+ * with one plan in flight on different streams race. */
 int gd_amr_reflux(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_old,
                   void *coarse_new, const void *fine_out_base, const void *fine_flux_base,
                   double gamma, double dt, const double *dt_dev, void *hip_stream);
@@ -338,8 +341,9 @@ int gd_amr_reflux(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const vo
 /* Steps 1-4: ghost fill, coarse step (coarse_in -> coarse_out), batched
  * fine step (fine_in_base -> fine_out_base with fluxes into fine_flux_base),
  * refluxing and averaging down into coarse_out; five launches on
- * hip_stream. A host dt is first stored in a device scalar of the plan, so
- * two calls with one plan in flight on different streams race. */
+ * hip_stream, six with a host dt, which is first stored in a device scalar
+ * of the plan. opts->bc is ignored. Calls with one plan in flight on
+ * different streams race (the plan's dt scalar and reflux scratch). */
 int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void *coarse_in,
                 void *coarse_out, void *fine_in_base, void *fine_out_base, void *fine_flux_base,
                 double gamma, double dt, const double *dt_dev, void *hip_stream);

@@ -8,10 +8,12 @@
 //   fill     one thread per cell of a fine patch's ghosted box (interior
 //            cells return at once): the value of the fine cell at the same
 //            place if a fine patch covers it, else the coarse parent;
-//   reflux   one thread per uncovered coarse cell that shares a face with a
-//            fine patch: for each such face, in a fixed order, the coarse
-//            flux is recomputed from the old coarse state and swapped for
-//            the mean of the four fine boundary fluxes;
+//   reflux   one thread per side of each coarse-fine face recomputes that
+//            side's predicted face state from the old coarse state (staged
+//            in the plan's scratch); then one thread per uncovered coarse
+//            cell next to a fine patch takes, face by face in a fixed order,
+//            the coarse flux from those states and swaps it for the mean of
+//            the four fine boundary fluxes;
 //   average  one thread per covered coarse cell: the mean of its eight
 //            children, summed as a fixed pairwise tree.
 // The work is a few percent of the step's and bound by latency and HBM
@@ -29,11 +31,9 @@ namespace {
 constexpr int FILL_BLOCK = 256;
 constexpr int SEAM_BLOCK = 128;
 
-__device__ __forceinline__ int wrap(int i, int n)
-{
-    i %= n;
-    return i < 0 ? i + n : i;
-}
+// i in [-n, 2n): one conditional add or subtract, no division (fine ghost
+// positions lie in [-2, 2 nc + 1) of a fine extent 2 nc >= 2)
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 template <typename T>
 __global__ __launch_bounds__(FILL_BLOCK) void fill_kernel(AmrTables t, const T *__restrict__ coarse,
@@ -80,7 +80,9 @@ __device__ __forceinline__ void coarse_prim(const AmrTables &t, const T *__restr
                                             int z, const Phys<T> &ph, T W[5], T &inv)
 {
     const int64_t n = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
-    const int c = (wrap(z, t.nc[2]) * t.nc[1] + wrap(y, t.nc[1])) * t.nc[0] + wrap(x, t.nc[0]);
+    // x, y, z lie in [-2, nc + 1): two conditional wraps cover nc >= 1
+    const int c = (wrap(wrap(z, t.nc[2]), t.nc[2]) * t.nc[1] + wrap(wrap(y, t.nc[1]), t.nc[1])) * t.nc[0] +
+                  wrap(wrap(x, t.nc[0]), t.nc[0]);
     T U[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) U[q] = u[c + q * n];
@@ -114,36 +116,54 @@ __device__ __forceinline__ void coarse_face_state(const AmrTables &t, const T *_
     face_state(Ws, Sd, half, out, ph, unused);
 }
 
-template <typename T, int LIM, int RS>
-__device__ __forceinline__ void coarse_face_flux(const AmrTables &t, const T *__restrict__ u, int right, int d,
-                                 T lam, const Phys<T> &ph, T F[5])
+// Variable index of component k of a state rotated to (rho, u_n, u_t1,
+// u_t2, p) with the cyclic order (d+1, d+2), as face_flux<RS, d> uses. The
+// rotation is done through memory addresses: with runtime d, selects between
+// register array elements are turned back into indexed private arrays.
+__device__ __forceinline__ int rotated_var(int k, int d)
 {
-    const int cr[3] = { right % t.nc[0], (right / t.nc[0]) % t.nc[1], right / (t.nc[0] * t.nc[1]) };
-    const int cl[3] = { cr[0] - (d == 0), cr[1] - (d == 1), cr[2] - (d == 2) };
-    T WL[5], WR[5];
-    coarse_face_state<T, LIM>(t, u, cl, d, T(0.5), lam, ph, WL);
-    coarse_face_state<T, LIM>(t, u, cr, d, T(-0.5), lam, ph, WR);
-    // rotate to (rho, u_n, u_t1, u_t2, p) with the cyclic order (d+1, d+2),
-    // as face_flux<RS, d> does, through value selects (a runtime axis index
-    // into the state arrays would put them in private memory)
-    T Lr[5] = { WL[0], d == 0 ? WL[1] : (d == 1 ? WL[2] : WL[3]),
-               d == 0 ? WL[2] : (d == 1 ? WL[3] : WL[1]), d == 0 ? WL[3] : (d == 1 ? WL[1] : WL[2]),
-               WL[4] };
-    T Rr[5] = { WR[0], d == 0 ? WR[1] : (d == 1 ? WR[2] : WR[3]),
-                d == 0 ? WR[2] : (d == 1 ? WR[3] : WR[1]), d == 0 ? WR[3] : (d == 1 ? WR[1] : WR[2]),
-                WR[4] };
-    T G[5];
-    riemann<RS>(Lr, Rr, ph, G);
-    F[0] = G[0];
-    F[1] = d == 0 ? G[1] : (d == 1 ? G[3] : G[2]);
-    F[2] = d == 0 ? G[2] : (d == 1 ? G[1] : G[3]);
-    F[3] = d == 0 ? G[3] : (d == 1 ? G[2] : G[1]);
-    F[4] = G[4];
+    if (k == 0 || k == 4) return k;
+    int v = k + d;
+    return v > 3 ? v - 3 : v;
 }
 
-template <typename T, int LIM, int RS>
-__global__ __launch_bounds__(SEAM_BLOCK) void seam_kernel(AmrTables t, const T *__restrict__ coarse_old,
-                                                          T *__restrict__ coarse_new,
+// Thread g < nfaces: the left state of face g (upper face state of the cell
+// below it along d); thread nfaces + g: its right state. Written to the
+// plan's scratch, already rotated, as [side][component][face].
+template <typename T, int LIM>
+__global__ __launch_bounds__(SEAM_BLOCK) void face_state_kernel(AmrTables t,
+                                                                const T *__restrict__ coarse_old,
+                                                                Scalars sc, double dx, double dt_host,
+                                                                const double *dt_dev)
+{
+    const int g = blockIdx.x * SEAM_BLOCK + threadIdx.x;
+    if (g >= 2 * t.nfaces) return;
+    const int side = g >= t.nfaces, f = g - side * t.nfaces;
+    const double dt = dt_dev ? *dt_dev : dt_host;
+    const T lam = T(dt / (2.0 * dx));
+    const Phys<T> ph = make_phys<T>(sc);
+    const AmrFace fc = t.faces[f];
+    const int d = fc.dside >> 1, r = fc.right;
+    const int c[3] = { r % t.nc[0] - (d == 0 && !side), (r / t.nc[0]) % t.nc[1] - (d == 1 && !side),
+                       r / (t.nc[0] * t.nc[1]) - (d == 2 && !side) };
+    T W[5];
+    coarse_face_state<T, LIM>(t, coarse_old, c, d, side ? T(-0.5) : T(0.5), lam, ph, W);
+    T *fs = (T *)t.fstate + (int64_t)side * 5 * t.nfaces + f;
+    // variable q sits at rotated component k with rotated_var(k, d) = q
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        int k = q;
+        if (q >= 1 && q <= 3) k = q - d < 1 ? q - d + 3 : q - d;
+        fs[(int64_t)k * t.nfaces] = W[q];
+    }
+}
+
+// Threads below ncells: refluxing of one uncovered cell, its faces in table
+// order (coarse flux from the staged face states, applied component by
+// component in the rotated frame); the rest: averaging down of one covered
+// cell.
+template <typename T, int RS>
+__global__ __launch_bounds__(SEAM_BLOCK) void seam_kernel(AmrTables t, T *__restrict__ coarse_new,
                                                           const T *__restrict__ fine_out,
                                                           const T *__restrict__ fine_flux,
                                                           Scalars sc, double dx, double dt_host,
@@ -153,27 +173,28 @@ __global__ __launch_bounds__(SEAM_BLOCK) void seam_kernel(AmrTables t, const T *
     const int64_t n = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
     if (g < t.ncells) {
         const double dt = dt_dev ? *dt_dev : dt_host;
-        const T c = T(dt / dx), lam = T(dt / (2.0 * dx));
+        const T c = T(dt / dx);
         const Phys<T> ph = make_phys<T>(sc);
-        const int o = t.cells[g];
-        T U[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) U[q] = coarse_new[o + q * n];
+        T *U = coarse_new + t.cells[g];
+        const T *fs = (const T *)t.fstate;
         for (int f = t.cell_start[g]; f < t.cell_start[g + 1]; ++f) {
             const AmrFace fc = t.faces[f];
             const int d = fc.dside >> 1, upper_side = fc.dside & 1;
-            T Fc[5];
-            coarse_face_flux<T, LIM, RS>(t, coarse_old, fc.right, d, lam, ph, Fc);
-            const T *b = fine_flux + fc.fine;
+            T Lr[5], Rr[5], G[5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const T *v = b + (int64_t)q * fc.vstride;
+            for (int k = 0; k < 5; ++k) {
+                Lr[k] = fs[(int64_t)k * t.nfaces + f];
+                Rr[k] = fs[(int64_t)(5 + k) * t.nfaces + f];
+            }
+            riemann<RS>(Lr, Rr, ph, G);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int q = rotated_var(k, d);
+                const T *v = fine_flux + fc.fine + (int64_t)q * fc.vstride;
                 T Ff = ((v[0] + v[1]) + (v[fc.row] + v[fc.row + 1])) * T(0.25);
-                U[q] += upper_side ? c * (Ff - Fc[q]) : c * (Fc[q] - Ff);
+                U[q * n] += upper_side ? c * (Ff - G[k]) : c * (G[k] - Ff);
             }
         }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) coarse_new[o + q * n] = U[q];
         return;
     }
     const int a = g - t.ncells;
@@ -198,11 +219,17 @@ int launch_seam_t(const AmrTables &t, const void *coarse_old, void *coarse_new, 
                   const void *fine_flux, const Scalars &sc, double dx, double dt,
                   const double *dt_dev, hipStream_t s)
 {
+    if (t.nfaces > 0) {
+        hipLaunchKernelGGL((face_state_kernel<T, LIM>), dim3((2 * t.nfaces + SEAM_BLOCK - 1) / SEAM_BLOCK),
+                           dim3(SEAM_BLOCK), 0, s, t, (const T *)coarse_old, sc, dx, dt, dt_dev);
+        int e = (int)hipGetLastError();
+        if (e) return e;
+    }
     const int total = t.ncells + t.ncover;
     if (total == 0) return 0;
-    hipLaunchKernelGGL((seam_kernel<T, LIM, RS>), dim3((total + SEAM_BLOCK - 1) / SEAM_BLOCK),
-                       dim3(SEAM_BLOCK), 0, s, t, (const T *)coarse_old, (T *)coarse_new,
-                       (const T *)fine_out, (const T *)fine_flux, sc, dx, dt, dt_dev);
+    hipLaunchKernelGGL((seam_kernel<T, RS>), dim3((total + SEAM_BLOCK - 1) / SEAM_BLOCK),
+                       dim3(SEAM_BLOCK), 0, s, t, (T *)coarse_new, (const T *)fine_out,
+                       (const T *)fine_flux, sc, dx, dt, dt_dev);
     return (int)hipGetLastError();
 }
 

@@ -809,6 +809,7 @@ struct gd_amr {
     int64_t in_end = 0, out_end = 0, fl_end = 0;   // fine buffer extents, elements
     void *mem = nullptr;            // one device block holding every table
     double *d_dt = nullptr;         // dt of gd_amr_step when given on the host
+                                    // (the tables also hold the reflux scratch)
     gd::AmrTables t{};
 };
 
@@ -996,7 +997,8 @@ int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int 
                     cover.push_back(c);
                 }
     }
-    if (fill.size() > 0x7fffffff / 2 || cells.size() + cover.size() > 0x7fffffff / 2)
+    if (fill.size() > 0x7fffffff / 2 || cells.size() + cover.size() > 0x7fffffff / 2 ||
+        faces.size() > 0x7fffffff / 4)
         return fail(ctx, GD_E_ARG, "hierarchy too large");
 
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
@@ -1009,6 +1011,7 @@ int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int 
     const size_t o_faces = blk.add(faces.size() * sizeof(gd::AmrFace));
     const size_t o_cover = blk.add(cover.size() * sizeof(gd::AmrCover));
     const size_t o_dt = blk.add(sizeof(double));
+    const size_t o_fs = blk.add(faces.size() * 10 * sizeof(double));
     gd_amr *a = new gd_amr();
     a->device = ctx->device;
     for (int k = 0; k < 3; ++k) a->nc[k] = nc[k];
@@ -1042,6 +1045,7 @@ int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int 
     t.nfill = (int32_t)fill.size();
     t.ncells = (int32_t)cells.size();
     t.ncover = (int32_t)cover.size();
+    t.nfaces = (int32_t)faces.size();
     t.owner = (const int32_t *)(base + o_owner);
     t.patches = (const gd::AmrPatch *)(base + o_patch);
     t.fill = (const gd::AmrFillItem *)(base + o_fill);
@@ -1050,6 +1054,7 @@ int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int 
     t.faces = (const gd::AmrFace *)(base + o_faces);
     t.cover = (const gd::AmrCover *)(base + o_cover);
     a->d_dt = (double *)(base + o_dt);
+    t.fstate = base + o_fs;
     *plan = a;
     return GD_OK;
 }

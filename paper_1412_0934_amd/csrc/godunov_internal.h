@@ -145,7 +145,7 @@ struct AmrCover {
 
 struct AmrTables {
     int32_t nc[3];
-    int32_t nfill, ncells, ncover;
+    int32_t nfill, ncells, ncover, nfaces;
     const int32_t *owner;           // coarse cell -> covering patch or -1
     const AmrPatch *patches;
     const AmrFillItem *fill;
@@ -153,12 +153,14 @@ struct AmrTables {
     const int32_t *cell_start;      // ncells + 1 offsets into faces
     const AmrFace *faces;
     const AmrCover *cover;
+    void *fstate;                   // scratch: 10 nfaces values (left, right face states)
 };
 
 int launch_amr_fill(int dtype, const AmrTables &t, const void *coarse, void *fine, hipStream_t s);
 
-// Refluxing of the uncovered cells and averaging down of the covered ones,
-// one launch; dt_dev, when not null, replaces dt.
+// Refluxing of the uncovered cells and averaging down of the covered ones
+// (two launches: face states, then corrections and averages); dt_dev, when
+// not null, replaces dt.
 int launch_amr_seam(int dtype, int limiter, int riemann, const AmrTables &t, const void *coarse_old,
                     void *coarse_new, const void *fine_out, const void *fine_flux,
                     const Scalars &sc, double dx_coarse, double dt, const double *dt_dev,
