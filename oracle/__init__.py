@@ -5,7 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package. The GPU library never
 loads it, and it shares no code with the GPU path: the C sources here are
 compiled by gcc into ``liboracle.so`` (double), ``liboracle_cs.so``
 (double complex, a complex-step tangent-linear model of the same forward code)
-and ``libmhd_oracle.so`` (the ideal-MHD step, wrapped by ``oracle.mhd``);
+``libmhd_oracle.so`` (the ideal-MHD step, wrapped by ``oracle.mhd``) and
+``libppm_oracle.so`` (the step with piecewise-parabolic reconstruction,
+reached through ``step(..., limiter="ppm" | "ppm_unlimited", ng=3)``);
 ``oracle.amr`` (Python) runs one step of a two-level hierarchy -- ghost fill,
 refluxing, averaging down -- around the single-patch step.
 
@@ -28,8 +30,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_DIR = os.environ.get("ORACLE_LIB_DIR", _HERE)
 _LIB = os.path.join(_LIB_DIR, "liboracle.so")
 _LIB_CS = os.path.join(_LIB_DIR, "liboracle_cs.so")
+_LIB_PPM = os.path.join(_LIB_DIR, "libppm_oracle.so")
 
-LIMITERS = {"minmod": 0, "mc": 1, "none": 2, "unlimited": 2}
+LIMITERS = {"minmod": 0, "mc": 1, "none": 2, "unlimited": 2, "ppm": 3, "ppm_unlimited": 4}
+PPM = ("ppm", "ppm_unlimited")
 RIEMANN = {"hllc": 0, "hll": 1}
 RHO_FLOOR = 1e-10
 P_FLOOR = 1e-10
@@ -47,6 +51,9 @@ def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE) -> 
     mhd_src = os.path.join(src_dir, "mhd_oracle.c")
     if os.path.exists(mhd_src):
         cmds.append(common + ["-o", os.path.join(out_dir, "libmhd_oracle.so"), mhd_src, "-lm"])
+    ppm_src = os.path.join(src_dir, "ppm_oracle.c")
+    if os.path.exists(ppm_src):
+        cmds.append(common + ["-o", os.path.join(out_dir, "libppm_oracle.so"), ppm_src, "-lm"])
     for cmd in cmds:
         if verbose:
             print(" ".join(cmd))
@@ -103,6 +110,27 @@ def _lib_cs() -> ctypes.CDLL:
     return lib
 
 
+def _lib_ppm() -> ctypes.CDLL:
+    lib = _load(_LIB_PPM)
+    P = ctypes.POINTER(_Problem)
+    dp = ctypes.c_void_p
+    lib.orc_step_ppm.argtypes = [P, dp, dp, dp]
+    lib.orc_step_ppm.restype = ctypes.c_long
+    lib.orc_ppm_edges.argtypes = [ctypes.c_int, dp, dp, dp]
+    lib.orc_ppm_edges.restype = None
+    return lib
+
+
+def ppm_edges(a5, limiter="ppm"):
+    """Edge values (a_L, a_R) of the parabola of the middle of five cell values."""
+    a = np.ascontiguousarray(a5, dtype=np.float64)
+    if a.shape != (5,):
+        raise ValueError("five cell values")
+    aL, aR = ctypes.c_double(), ctypes.c_double()
+    _lib_ppm().orc_ppm_edges(LIMITERS[limiter], a.ctypes.data, ctypes.byref(aL), ctypes.byref(aR))
+    return aL.value, aR.value
+
+
 def _problem(shape, *, gamma, dx, dt, ng, periodic, limiter, riemann, rho_floor, p_floor):
     if len(shape) != 4 or shape[0] != 5:
         raise ValueError(f"state must have shape (5, z, y, x), got {shape}")
@@ -139,7 +167,8 @@ def step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", riemann="h
                  limiter=limiter, riemann=riemann, rho_floor=rho_floor, p_floor=p_floor)
     out = np.empty((5, P.nz, P.ny, P.nx))
     bflux = np.empty(bflux_size(P.nx, P.ny, P.nz))
-    hits = _lib().orc_step(ctypes.byref(P), u.ctypes.data, out.ctypes.data, bflux.ctypes.data)
+    fn = _lib_ppm().orc_step_ppm if limiter in PPM else _lib().orc_step
+    hits = fn(ctypes.byref(P), u.ctypes.data, out.ctypes.data, bflux.ctypes.data)
     if hits < 0:
         raise ValueError("oracle rejected the problem")
     return out, bflux, int(hits)

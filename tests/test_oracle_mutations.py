@@ -17,9 +17,9 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 FWD, ADJ, MHD = "godunov_oracle.c", "godunov_oracle_adjoint.c", "mhd_oracle.c"
-AMR = "amr.py"
+AMR, PPMF = "amr.py", "ppm_oracle.c"
 PINS = {FWD: "test_oracle_pins.py", ADJ: "test_oracle_pins.py", MHD: "test_mhd_oracle_pins.py",
-        AMR: "test_amr_oracle_pins.py"}
+        AMR: "test_amr_oracle_pins.py", PPMF: "test_ppm_oracle_pins.py"}
 
 # (file, text, replacement, the mistake it plants)
 MUTATIONS = [
@@ -79,6 +79,26 @@ MUTATIONS = [
      "ghost position off by one"),
     (AMR, "gz - 2 * h.lo[q][2] + 2,", "gz - 2 * h.lo[q][2] + 1,", "fine source cell off by one"),
     (AMR, "dxc / 2, dt,", "dxc, dt,", "fine patches stepped at the coarse spacing"),
+    (PPMF, "return 0.5 * (a0 + ap) - (d1 - d0) / 6.0;", "return 0.5 * (a0 + ap) + (d1 - d0) / 6.0;",
+     "PPM interface correction sign"),
+    (PPMF, "return 0.5 * (a0 + ap) - (d1 - d0) / 6.0;", "return 0.5 * (a0 + ap) - (d1 - d0) / 3.0;",
+     "PPM interface correction weight"),
+    (PPMF, "return 0.5 * (ap - am);", "return 0.5 * (ap - a0);", "unlimited PPM slope one-sided"),
+    (PPMF, "l = 3.0 * a0 - 2.0 * r;", "l = 3.0 * a0 - 2.0 * l;", "PPM overshoot fix of the left edge"),
+    (PPMF, "r = 3.0 * a0 - 2.0 * l;", "r = 2.0 * a0 - l;", "PPM overshoot fix of the right edge"),
+    (PPMF, "            l = a0;\n            r = a0;", "            r = a0;",
+     "PPM extremum flattens one edge only"),
+    (PPMF, "if (limiter == LIM_PPM) {", "if (limiter == LIM_PPM_NONE) {",
+     "monotonicity applied to the unlimited parabola"),
+    (PPMF, "s[d][q] = aR - aL;", "s[d][q] = aL - aR;", "PPM predictor slope sign"),
+    (PPMF, "WL[q] = Ws[5 * cl + q] + (E[30 * cl + 10 * d + 5 + q] - W[5 * cl + q]);",
+     "WL[q] = Ws[5 * cl + q] + (E[30 * cl + 10 * d + q] - W[5 * cl + q]);",
+     "left face state from the lower edge"),
+    (PPMF, "WR[q] = Ws[5 * cr + q] + (E[30 * cr + 10 * d + q] - W[5 * cr + q]);",
+     "WR[q] = Ws[5 * cr + q] - (E[30 * cr + 10 * d + q] - W[5 * cr + q]);",
+     "right face state offset sign"),
+    (PPMF, "size_t cpp = ext3_index(&B, i + 2 * di, j + 2 * dj, k + 2 * dk);",
+     "size_t cpp = ext3_index(&B, i + di, j + dj, k + dk);", "PPM stencil's far right cell"),
 ]
 
 
@@ -87,7 +107,7 @@ def _run_mutant(case):
     if fname == AMR:
         return _run_python_mutant(case)
     with tempfile.TemporaryDirectory() as tmp:
-        for f in (FWD, ADJ, MHD):
+        for f in (FWD, ADJ, MHD, PPMF):
             shutil.copy(os.path.join(ORACLE, f), tmp)
         path = os.path.join(tmp, fname)
         src = open(path).read()
