@@ -72,7 +72,11 @@ typedef enum {
 
 typedef enum { GD_F64 = 0, GD_F32 = 1 } gd_dtype;          /* dtype of every array */
 typedef enum { GD_GHOSTED = 0, GD_PERIODIC = 1 } gd_bc;      /* layout of the input */
-typedef enum { GD_MINMOD = 0, GD_MC = 1, GD_UNLIMITED = 2 } gd_limiter;
+typedef enum {
+    GD_MINMOD = 0, GD_MC = 1, GD_UNLIMITED = 2,
+    GD_PPM = 3,             /* piecewise-parabolic reconstruction (see below) */
+    GD_PPM_UNLIMITED = 4    /* the same parabola without its limiters */
+} gd_limiter;
 typedef enum { GD_HLLC = 0, GD_HLL = 1 } gd_riemann;
 
 /* Scheme options. minmod(a,b) = 0 unless a, b share a sign, else the one of

@@ -28,6 +28,17 @@ struct BatchCache {
     size_t cap_patches = 0, cap_items = 0, cap_cfl = 0;
 };
 
+struct PpmCache {
+    std::vector<gd_patch> host;
+    int dtype = -1;
+    gd::PatchDesc *d_patches = nullptr;
+    gd::PpmItem *d_pitems = nullptr, *d_uitems = nullptr;
+    int64_t *d_soff = nullptr;
+    int npitems = 0, nuitems = 0;
+    int64_t scratch_elems = 0;
+    size_t cap_patches = 0, cap_pitems = 0, cap_uitems = 0, cap_soff = 0;
+};
+
 }  // namespace
 
 struct gd_ctx {
@@ -44,6 +55,10 @@ struct gd_ctx {
     size_t adj_bytes = 0;
     void *d_mhd = nullptr;               // MHD step scratch (grown on demand)
     size_t mhd_bytes = 0;
+    void *d_ppm = nullptr;               // PPM face-state scratch (grown on demand)
+    size_t ppm_bytes = 0;
+    PpmCache ppm;                        // batch tables of the PPM step
+    BatchCache ppm_cfl;                  // CFL tables over the PPM batch's outputs
     // tuned configuration per dtype (index 0: FP64, 1: FP32)
     int zlen_single[2] = { 32, 32 };
     int shape_single[2] = { gd::TILE_16x16, gd::TILE_16x16 };
@@ -76,7 +91,7 @@ int check_opts(gd_ctx *ctx, const gd_opts *o)
     if (!o) return fail(ctx, GD_E_ARG, "opts is NULL");
     if (o->dtype != GD_F64 && o->dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", o->dtype);
     if (o->bc != GD_GHOSTED && o->bc != GD_PERIODIC) return fail(ctx, GD_E_ARG, "bad bc %d", o->bc);
-    if (o->limiter < GD_MINMOD || o->limiter > GD_UNLIMITED)
+    if (o->limiter < GD_MINMOD || o->limiter > GD_PPM_UNLIMITED)
         return fail(ctx, GD_E_ARG, "bad limiter %d", o->limiter);
     if (o->riemann != GD_HLLC && o->riemann != GD_HLL)
         return fail(ctx, GD_E_ARG, "bad riemann solver %d", o->riemann);
@@ -86,6 +101,14 @@ int check_opts(gd_ctx *ctx, const gd_opts *o)
 }
 
 size_t elem_size(const gd_opts *o) { return o->dtype == GD_F32 ? 4 : 8; }
+
+bool is_ppm(const gd_opts *o) { return o->limiter == GD_PPM || o->limiter == GD_PPM_UNLIMITED; }
+
+int reject_ppm(gd_ctx *ctx, const gd_opts *o, const char *what)
+{
+    if (is_ppm(o)) return fail(ctx, GD_E_UNSUPPORTED, "%s does not take the PPM reconstruction", what);
+    return GD_OK;
+}
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
 {
@@ -229,9 +252,10 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
     return GD_OK;
 }
 
-int build_cfl_tables(gd_ctx *ctx, bool periodic, int npatch, const gd_patch *patches, hipStream_t s)
+int build_cfl_tables(gd_ctx *ctx, bool periodic, int npatch, const gd_patch *patches, hipStream_t s,
+                     BatchCache *cache = nullptr)
 {
-    BatchCache &c = ctx->cfl;
+    BatchCache &c = cache ? *cache : ctx->cfl;
     int tag = periodic ? 1 : 0;
     if (c.dtype == tag && same_patches(c, npatch, patches)) return GD_OK;
     std::vector<gd::PatchDesc> desc(npatch);
@@ -309,6 +333,13 @@ int gd_destroy(gd_ctx *ctx)
     }
     if (ctx->d_adj) (void)hipFree(ctx->d_adj);
     if (ctx->d_mhd) (void)hipFree(ctx->d_mhd);
+    if (ctx->d_ppm) (void)hipFree(ctx->d_ppm);
+    if (ctx->ppm.d_patches) (void)hipFree(ctx->ppm.d_patches);
+    if (ctx->ppm.d_pitems) (void)hipFree(ctx->ppm.d_pitems);
+    if (ctx->ppm.d_uitems) (void)hipFree(ctx->ppm.d_uitems);
+    if (ctx->ppm.d_soff) (void)hipFree(ctx->ppm.d_soff);
+    if (ctx->ppm_cfl.d_patches) (void)hipFree(ctx->ppm_cfl.d_patches);
+    if (ctx->ppm_cfl.d_cfl_items) (void)hipFree(ctx->ppm_cfl.d_cfl_items);
     if (ctx->d_u64) (void)hipFree(ctx->d_u64);
     if (ctx->d_u32) (void)hipFree(ctx->d_u32);
     delete ctx;
@@ -349,6 +380,62 @@ int gd_reset_stats(gd_ctx *ctx)
 
 namespace {
 
+int ensure_ppm_scratch(gd_ctx *ctx, size_t need)
+{
+    if (need <= ctx->ppm_bytes && ctx->d_ppm) return GD_OK;
+    // grow the scratch; work already queued may still use the old one
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "PPM scratch");
+    if (ctx->d_ppm) (void)hipFree(ctx->d_ppm);
+    ctx->d_ppm = nullptr;
+    ctx->ppm_bytes = 0;
+    if (hipMalloc(&ctx->d_ppm, need) != hipSuccess)
+        return fail(ctx, GD_E_NOMEM, "PPM scratch of %zu bytes", need);
+    ctx->ppm_bytes = need;
+    return GD_OK;
+}
+
+// Work tables of a PPM batch: 256-cell pieces of each patch's scratch box
+// (predict) and of its interior (update), and each patch's scratch offset.
+int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream_t s)
+{
+    PpmCache &c = ctx->ppm;
+    if ((int)c.host.size() == npatch &&
+        std::memcmp(c.host.data(), patches, npatch * sizeof(gd_patch)) == 0)
+        return GD_OK;
+    std::vector<gd::PatchDesc> desc(npatch);
+    std::vector<gd::PpmItem> pit, uit;
+    std::vector<int64_t> soff(npatch);
+    int64_t off = 0;
+    for (int i = 0; i < npatch; ++i) {
+        desc[i] = to_desc(patches[i], false);
+        soff[i] = off;
+        const int64_t box = gd::ppm_box_cells(desc[i]);
+        const int64_t cells = (int64_t)patches[i].nx * patches[i].ny * patches[i].nz;
+        if (box >= 0x7fffffffLL) return fail(ctx, GD_E_ARG, "patch %d too large for the PPM step", i);
+        off += 30 * box;
+        for (int64_t a = 0; a < box; a += 256) pit.push_back(gd::PpmItem{ i, (int32_t)a });
+        for (int64_t a = 0; a < cells; a += 256) uit.push_back(gd::PpmItem{ i, (int32_t)a });
+    }
+    if (pit.size() > 0x7fffffff || uit.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many PPM items");
+    int r;
+    if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
+    if ((r = ensure_capacity(ctx, &c.d_pitems, &c.cap_pitems, pit.size()))) return r;
+    if ((r = ensure_capacity(ctx, &c.d_uitems, &c.cap_uitems, uit.size()))) return r;
+    if ((r = ensure_capacity(ctx, &c.d_soff, &c.cap_soff, soff.size()))) return r;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_pitems, pit.data(), pit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_uitems, uit.data(), uit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_soff, soff.data(), soff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of PPM tables");
+    c.host.assign(patches, patches + npatch);
+    c.npitems = (int)pit.size();
+    c.nuitems = (int)uit.size();
+    c.scratch_elems = off;
+    return GD_OK;
+}
+
 int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
               const void *u_in, void *u_out, void *bflux, double gamma, double dx, double dt,
               const double *dt_dev, double cfl, double *dt_next, void *hip_stream)
@@ -369,6 +456,8 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     if (dt_next && !(cfl > 0.0)) return fail(ctx, GD_E_ARG, "cfl must be > 0");
     if (dt_next && (overlap(dt_next, 8, u_in, nin) || overlap(dt_next, 8, u_out, nout)))
         return fail(ctx, GD_E_ARG, "dt_next overlaps a state array");
+    if (is_ppm(opts) && !periodic && ng < 3)
+        return fail(ctx, GD_E_ARG, "the PPM step needs ng >= 3 in ghosted mode (got %d)", ng);
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
 
@@ -377,6 +466,23 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     P.in_off = 0; P.out_off = 0; P.flux_off = bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    if (is_ppm(opts)) {
+        hipStream_t s = (hipStream_t)hip_stream;
+        if ((r = ensure_ppm_scratch(ctx, (size_t)gd::ppm_box_cells(P) * 30 * es))) return r;
+        int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, P, nullptr, nullptr, 0,
+                               nullptr, 0, nullptr, u_in, u_out, bflux, ctx->d_ppm, dt_dev, sc,
+                               ctx->d_u64, s);
+        if (e) return hip_fail(ctx, e, "PPM step launch");
+        if (dt_next) {
+            // the CFL step of the new state, reduced over u_out
+            gd::PatchDesc Po = P;
+            Po.periodic = 1; Po.ng = 0;
+            e = gd::launch_cfl_single(opts->dtype, Po, u_out, sc, cfl, dt_next, ctx->d_u64 + 2,
+                                      ctx->d_u32 + 3, s);
+            if (e) return hip_fail(ctx, e, "PPM step CFL launch");
+        }
+        return GD_OK;
+    }
     gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
     int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann,
                             ctx->shape_single[opts->dtype], P, u_in, u_out, bflux, dt_dev, sc,
@@ -414,9 +520,37 @@ int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_pat
     if (dt_next && (overlap(dt_next, 8, u_in_base, in_end * es) ||
                     overlap(dt_next, 8, u_out_base, out_end * es)))
         return fail(ctx, GD_E_ARG, "dt_next overlaps a state array");
+    if (is_ppm(opts))
+        for (int i = 0; i < npatch; ++i)
+            if (patches[i].ng < 3)
+                return fail(ctx, GD_E_ARG, "patch %d: the PPM step needs ng >= 3 (got %d)", i,
+                            patches[i].ng);
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (is_ppm(opts)) {
+        gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+        if ((r = build_ppm_tables(ctx, npatch, patches, s))) return r;
+        const PpmCache &c = ctx->ppm;
+        if ((r = ensure_ppm_scratch(ctx, (size_t)c.scratch_elems * es))) return r;
+        gd::PatchDesc none{};
+        int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, none, c.d_patches, c.d_pitems,
+                               c.npitems, c.d_uitems, c.nuitems, c.d_soff, u_in_base, u_out_base,
+                               bflux_base, ctx->d_ppm, dt_dev, sc, ctx->d_u64, s);
+        if (e) return hip_fail(ctx, e, "PPM batched step launch");
+        if (dt_next) {
+            // the batch's CFL step, reduced over the outputs (interior layout)
+            std::vector<gd_patch> outs(patches, patches + npatch);
+            for (auto &p : outs) { p.u_in_off = p.u_out_off; p.ng = 0; }
+            if ((r = build_cfl_tables(ctx, true, npatch, outs.data(), s, &ctx->ppm_cfl))) return r;
+            const BatchCache &cc = ctx->ppm_cfl;
+            int grid = std::min(cc.ncfl, 8 * ctx->num_cus);
+            e = gd::launch_cfl(opts->dtype, cc.d_patches, cc.d_cfl_items, cc.ncfl, u_out_base, sc, cfl,
+                               dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3, std::max(grid, 1), s);
+            if (e) return hip_fail(ctx, e, "PPM batched CFL launch");
+        }
+        return GD_OK;
+    }
     if ((r = build_step_tables(ctx, opts->dtype, ctx->shape_batched[opts->dtype],
                                ctx->zpolicy_batched[opts->dtype], npatch, patches, s)))
         return r;
@@ -509,6 +643,7 @@ int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int n
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the adjoint"))) return r;
     if (opts->dtype != GD_F64) return fail(ctx, GD_E_UNSUPPORTED, "the adjoint is FP64 only");
     const bool periodic = opts->bc == GD_PERIODIC;
     if ((r = check_extents(ctx, nx, ny, nz, ng, periodic))) return r;
@@ -592,6 +727,7 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
     const int dt_i = opts->dtype;
     const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
                             gd::TILE_24x8 };
@@ -634,6 +770,7 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
     const int dt_i = opts->dtype;
     const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
                             gd::TILE_24x8 };
@@ -704,6 +841,7 @@ int check_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, double g
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the MHD step"))) return r;
     if (opts->bc != GD_PERIODIC)
         return fail(ctx, GD_E_UNSUPPORTED, "the MHD step supports periodic boxes only");
     if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, GD_E_ARG, "extents must be >= 1 (%d,%d,%d)", nx, ny, nz);
@@ -849,6 +987,7 @@ int amr_seam_impl(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const vo
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the AMR seams"))) return r;
     if ((r = check_plan(ctx, plan))) return r;
     if ((r = check_scalars(ctx, gamma, plan->dx, dt_dev ? 0.0 : dt))) return r;
     const bool fine = !plan->fine.empty();
@@ -1088,6 +1227,7 @@ int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void
 {
     int r;
     if ((r = check_opts(ctx, opts))) return r;
+    if ((r = reject_ppm(ctx, opts, "the AMR seams"))) return r;
     if ((r = check_plan(ctx, plan))) return r;
     if ((r = check_scalars(ctx, gamma, plan->dx, dt_dev ? 0.0 : dt))) return r;
     const bool fine = !plan->fine.empty();

@@ -169,4 +169,23 @@ int launch_amr_seam(int dtype, int limiter, int riemann, const AmrTables &t, con
 // *dst = v, stream-ordered (capturable, unlike a host-to-device copy).
 int launch_set_scalar(double *dst, double v, hipStream_t s);
 
+// Piecewise-parabolic reconstruction (godunov_ppm.hip). A batched launch takes
+// 256-cell pieces of each patch: of its scratch box for the predict kernel,
+// of its interior for the update kernel.
+struct PpmItem {
+    int32_t patch, start;
+};
+
+// Cells of a patch's PPM scratch box: the interior (periodic) or the interior
+// plus one layer (ghosted); the scratch holds 30 values per box cell.
+int64_t ppm_box_cells(const PatchDesc &P);
+
+// One PPM step (limiter 3: limited parabola, 4: unlimited). With patches ==
+// nullptr the single patch P1 is stepped; else the batch described by the
+// device tables (soff: per-patch scratch offsets in elements).
+int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
+               const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+               const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
+               const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s);
+
 }  // namespace gd

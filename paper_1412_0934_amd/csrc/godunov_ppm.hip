@@ -1,0 +1,368 @@
+// gfx950 kernels of the Godunov step with piecewise-parabolic reconstruction
+// (the PPM member of the reconstructions the paper lists beside PLM and TVD,
+// Sec. 2; Enzo's hydro solver, Sec. 4).
+//
+// Per axis and primitive variable the parabola of Colella & Woodward (1984)
+// replaces the limited slope of the PLM step: interface values
+// a_{i+1/2} = (a_i + a_{i+1})/2 - (da_{i+1} - da_i)/6 with MC-limited (or,
+// unlimited, central) slopes da, then -- limited variant -- flattening at a
+// local extremum and the overshoot corrections a_L = 3a - 2a_R or
+// a_R = 3a - 2a_L. The Hancock half step uses the slopes a_R - a_L; the face
+// states are W* + (a_R - W) on the upper face and W* + (a_L - W) on the lower.
+//
+// Two launches per step, over a scratch of 30 values per predicted cell:
+//   ppm_predict  one thread per cell whose face states some face needs (the
+//                interior and, for a ghosted patch, the face ghosts of depth
+//                1): per axis the five-cell stencil -> edges, then the
+//                predictor and the six floored face states, stored SoA;
+//   ppm_update   one thread per interior cell: its six face fluxes from the
+//                staged states (a face shared by two cells is evaluated by
+//                both from the same inputs, so both get the same bits), the
+//                update, the boundary-flux sheets.
+// Both run over one patch (the grid covers it) or a batch (each workgroup
+// takes a 256-cell piece of one patch from a host-built table).
+#include "godunov_cell.h"
+#include "godunov_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gd {
+
+namespace {
+
+constexpr int PPM_BLOCK = 256;
+enum { PPM_LIMITED = 0, PPM_CENTRAL = 1 };
+
+// Addressing of a patch's input: ghosted [5][nz+2ng][ny+2ng][nx+2ng], or a
+// periodic box [5][nz][ny][nx] whose neighbours wrap (coordinates in
+// [-2n, 3n) here).
+struct Addr {
+    int nx, ny, nz, ng, periodic;
+    int gx, gy;
+    int64_t vs;
+
+    __device__ __forceinline__ static int wrap(int i, int n)
+    {
+        i = i < 0 ? i + n : (i >= n ? i - n : i);
+        return i < 0 ? i + n : (i >= n ? i - n : i);
+    }
+    __device__ __forceinline__ int64_t at(int i, int j, int k) const
+    {
+        if (periodic) return ((int64_t)wrap(k, nz) * ny + wrap(j, ny)) * nx + wrap(i, nx);
+        return ((int64_t)(k + ng) * gy + (j + ng)) * gx + (i + ng);
+    }
+};
+
+__device__ __forceinline__ Addr make_addr(const PatchDesc &P)
+{
+    Addr a;
+    a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.ng = P.ng; a.periodic = P.periodic;
+    a.gx = P.periodic ? P.nx : P.nx + 2 * P.ng;
+    a.gy = P.periodic ? P.ny : P.ny + 2 * P.ng;
+    const int gz = P.periodic ? P.nz : P.nz + 2 * P.ng;
+    a.vs = (int64_t)a.gx * a.gy * gz;
+    return a;
+}
+
+// The scratch box of a patch: the interior for a periodic box, the interior
+// plus one layer (whose face-ghost cells are predicted) for a ghosted one.
+struct Box {
+    int e, bx, by, bz;
+    int64_t n;
+};
+
+__device__ __forceinline__ Box make_box(const PatchDesc &P)
+{
+    Box b;
+    b.e = P.periodic ? 0 : 1;
+    b.bx = P.nx + 2 * b.e; b.by = P.ny + 2 * b.e; b.bz = P.nz + 2 * b.e;
+    b.n = (int64_t)b.bx * b.by * b.bz;
+    return b;
+}
+
+template <int MODE, typename T>
+__device__ __forceinline__ T ppm_slope(T am, T a0, T ap)
+{
+    if constexpr (MODE == PPM_CENTRAL) return T(0.5) * (ap - am);
+    else return limited_slope<LIM_MC>(a0 - am, ap - a0);
+}
+
+// Interface value between the cells holding a0 and ap.
+template <int MODE, typename T>
+__device__ __forceinline__ T ppm_interface(T am, T a0, T ap, T app)
+{
+    T d0 = ppm_slope<MODE>(am, a0, ap);
+    T d1 = ppm_slope<MODE>(a0, ap, app);
+    return T(0.5) * (a0 + ap) - (d1 - d0) / T(6);
+}
+
+template <int MODE, typename T>
+__device__ __forceinline__ void ppm_edges(T amm, T am, T a0, T ap, T app, T &aL, T &aR)
+{
+    T l = ppm_interface<MODE>(amm, am, a0, ap);
+    T r = ppm_interface<MODE>(am, a0, ap, app);
+    if constexpr (MODE == PPM_LIMITED) {
+        if ((r - a0) * (a0 - l) <= T(0)) {
+            l = a0;
+            r = a0;
+        } else {
+            T D = r - l, m = a0 - T(0.5) * (l + r);
+            // the threshold is divided, not multiplied by 1/6, so that the
+            // branch matches the definition's rounding
+            if (D * m > D * D / T(6)) l = T(3) * a0 - T(2) * r;
+            else if (-(D * D) / T(6) > D * m) r = T(3) * a0 - T(2) * l;
+        }
+    }
+    aL = l;
+    aR = r;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_prim(const T *__restrict__ u, const Addr &A, int i, int j, int k,
+                                          const Phys<T> &ph, T W[5], T &inv, int &hits)
+{
+    const int64_t o = A.at(i, j, k);
+    T U[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) U[q] = u[o + q * A.vs];
+    prim_from_cons(U, W, inv, ph, hits);
+}
+
+__device__ __forceinline__ void count_hits(int hits, unsigned long long *counter)
+{
+    if (hits) atomicAdd(counter, (unsigned long long)hits);
+}
+
+template <typename T, int MODE, bool BATCHED>
+__global__ __launch_bounds__(PPM_BLOCK) void ppm_predict_kernel(
+    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmItem *__restrict__ items,
+    const int64_t *__restrict__ soff, const T *__restrict__ u_base, T *__restrict__ scratch,
+    const double *dt_dev, Scalars sc, unsigned long long *hits_ctr)
+{
+    PatchDesc P;
+    int start;
+    int64_t so = 0;
+    if constexpr (BATCHED) {
+        const PpmItem it = items[blockIdx.x];
+        P = patches[it.patch];
+        start = it.start;
+        so = soff[it.patch];
+    } else {
+        P = P1;
+        start = blockIdx.x * PPM_BLOCK;
+    }
+    const Box B = make_box(P);
+    const int idx = start + (int)threadIdx.x;
+    if (idx >= B.n) return;
+    const int i = idx % B.bx - B.e, j = (idx / B.bx) % B.by - B.e, k = idx / (B.bx * B.by) - B.e;
+    if (!P.periodic) {
+        const int di = i < 0 ? -i : (i >= P.nx ? i - P.nx + 1 : 0);
+        const int dj = j < 0 ? -j : (j >= P.ny ? j - P.ny + 1 : 0);
+        const int dk = k < 0 ? -k : (k >= P.nz ? k - P.nz + 1 : 0);
+        if (di + dj + dk > 1) return;       // an edge or corner of the box: never needed
+    }
+    const Addr A = make_addr(P);
+    const T *__restrict__ u = u_base + P.in_off;
+    const Phys<T> ph = make_phys<T>(sc);
+    const double dt = dt_dev ? *dt_dev : P.dt;
+    const T lam = T(dt / (2.0 * P.dx));
+    int hits = 0;
+
+    T W[5], inv;
+    load_prim(u, A, i, j, k, ph, W, inv, hits);
+    T aL[3][5], aR[3][5], S[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int di = d == 0, dj = d == 1, dk = d == 2;
+        T Wmm[5], Wm[5], Wp[5], Wpp[5], unused;
+        load_prim(u, A, i - 2 * di, j - 2 * dj, k - 2 * dk, ph, Wmm, unused, hits);
+        load_prim(u, A, i - di, j - dj, k - dk, ph, Wm, unused, hits);
+        load_prim(u, A, i + di, j + dj, k + dk, ph, Wp, unused, hits);
+        load_prim(u, A, i + 2 * di, j + 2 * dj, k + 2 * dk, ph, Wpp, unused, hits);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            ppm_edges<MODE>(Wmm[q], Wm[q], W[q], Wp[q], Wpp[q], aL[d][q], aR[d][q]);
+            S[d][q] = aR[d][q] - aL[d][q];
+        }
+    }
+    T Ws[5];
+    predictor(W, inv, S[0], S[1], S[2], lam, ph.gamma, Ws);
+    T *__restrict__ out = scratch + so + idx;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T lo[5], hi[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            lo[q] = Ws[q] + (aL[d][q] - W[q]);
+            hi[q] = Ws[q] + (aR[d][q] - W[q]);
+        }
+        hits += (lo[0] < ph.rho_floor) + (lo[4] < ph.p_floor) + (hi[0] < ph.rho_floor) +
+                (hi[4] < ph.p_floor);
+        lo[0] = fmax(lo[0], ph.rho_floor); lo[4] = fmax(lo[4], ph.p_floor);
+        hi[0] = fmax(hi[0], ph.rho_floor); hi[4] = fmax(hi[4], ph.p_floor);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            out[(int64_t)((2 * d) * 5 + q) * B.n] = lo[q];
+            out[(int64_t)((2 * d + 1) * 5 + q) * B.n] = hi[q];
+        }
+    }
+    count_hits(hits, hits_ctr);
+}
+
+// Scratch index of cell (i, j, k) of the box (periodic boxes wrap).
+__device__ __forceinline__ int64_t box_at(const Box &B, const PatchDesc &P, int i, int j, int k)
+{
+    if (P.periodic) {
+        i = i < 0 ? i + P.nx : (i >= P.nx ? i - P.nx : i);
+        j = j < 0 ? j + P.ny : (j >= P.ny ? j - P.ny : j);
+        k = k < 0 ? k + P.nz : (k >= P.nz ? k - P.nz : k);
+        return ((int64_t)k * P.ny + j) * P.nx + i;
+    }
+    return ((int64_t)(k + 1) * B.by + (j + 1)) * B.bx + (i + 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_state(const T *__restrict__ s, int64_t n, int slot, T W[5])
+{
+#pragma unroll
+    for (int q = 0; q < 5; ++q) W[q] = s[(int64_t)(slot * 5 + q) * n];
+}
+
+template <typename T, int RS, bool BATCHED>
+__global__ __launch_bounds__(PPM_BLOCK) void ppm_update_kernel(
+    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmItem *__restrict__ items,
+    const int64_t *__restrict__ soff, const T *__restrict__ u_base, const T *__restrict__ scratch,
+    T *__restrict__ out_base, T *__restrict__ bflux_base, const double *dt_dev, Scalars sc)
+{
+    PatchDesc P;
+    int start;
+    int64_t so = 0;
+    if constexpr (BATCHED) {
+        const PpmItem it = items[blockIdx.x];
+        P = patches[it.patch];
+        start = it.start;
+        so = soff[it.patch];
+    } else {
+        P = P1;
+        start = blockIdx.x * PPM_BLOCK;
+    }
+    const int64_t ncell = (int64_t)P.nx * P.ny * P.nz;
+    const int idx = start + (int)threadIdx.x;
+    if (idx >= ncell) return;
+    const int i = idx % P.nx, j = (idx / P.nx) % P.ny, k = idx / (P.nx * P.ny);
+    const Box B = make_box(P);
+    const T *__restrict__ s = scratch + so;
+    const Phys<T> ph = make_phys<T>(sc);
+    const double dt = dt_dev ? *dt_dev : P.dt;
+    const T c = T(dt / P.dx);
+    const int64_t me = box_at(B, P, i, j, k);
+
+    T Fm[3][5], Fp[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int di = d == 0, dj = d == 1, dk = d == 2;
+        const int64_t left = box_at(B, P, i - di, j - dj, k - dk);
+        const int64_t right = box_at(B, P, i + di, j + dj, k + dk);
+        T WL[5], WR[5];
+        load_state(s + left, B.n, 2 * d + 1, WL);
+        load_state(s + me, B.n, 2 * d, WR);
+        if (d == 0) face_flux<RS, 0>(WL, WR, ph, Fm[d]);
+        else if (d == 1) face_flux<RS, 1>(WL, WR, ph, Fm[d]);
+        else face_flux<RS, 2>(WL, WR, ph, Fm[d]);
+        load_state(s + me, B.n, 2 * d + 1, WL);
+        load_state(s + right, B.n, 2 * d, WR);
+        if (d == 0) face_flux<RS, 0>(WL, WR, ph, Fp[d]);
+        else if (d == 1) face_flux<RS, 1>(WL, WR, ph, Fp[d]);
+        else face_flux<RS, 2>(WL, WR, ph, Fp[d]);
+    }
+    const Addr A = make_addr(P);
+    const T *__restrict__ u = u_base + P.in_off + A.at(i, j, k);
+    T *__restrict__ o = out_base + P.out_off + idx;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        T div = ((Fp[0][q] - Fm[0][q]) + (Fp[1][q] - Fm[1][q])) + (Fp[2][q] - Fm[2][q]);
+        o[(int64_t)q * ncell] = u[(int64_t)q * A.vs] - c * div;
+    }
+    if (bflux_base && P.flux_off >= 0) {
+        T *bf = bflux_base + P.flux_off;
+        const int64_t sx = (int64_t)P.nz * P.ny, sy = (int64_t)P.nz * P.nx, sz = (int64_t)P.ny * P.nx;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            if (i == 0) bf[q * sx + (int64_t)k * P.ny + j] = Fm[0][q];
+            if (i == P.nx - 1) bf[5 * sx + q * sx + (int64_t)k * P.ny + j] = Fp[0][q];
+            if (j == 0) bf[10 * sx + q * sy + (int64_t)k * P.nx + i] = Fm[1][q];
+            if (j == P.ny - 1) bf[10 * sx + 5 * sy + q * sy + (int64_t)k * P.nx + i] = Fp[1][q];
+            if (k == 0) bf[10 * sx + 10 * sy + q * sz + (int64_t)j * P.nx + i] = Fm[2][q];
+            if (k == P.nz - 1) bf[10 * sx + 10 * sy + 5 * sz + q * sz + (int64_t)j * P.nx + i] = Fp[2][q];
+        }
+    }
+}
+
+template <typename T, int MODE, int RS>
+int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmItem *pitems, int npitems,
+                 const PpmItem *uitems, int nuitems, const int64_t *soff, const void *u_in,
+                 void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
+                 unsigned long long *hits, hipStream_t s)
+{
+    if (patches) {
+        if (npitems == 0 || nuitems == 0) return 0;
+        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, true>), dim3(npitems), dim3(PPM_BLOCK), 0, s,
+                           P1, patches, pitems, soff, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
+        hipLaunchKernelGGL((ppm_update_kernel<T, RS, true>), dim3(nuitems), dim3(PPM_BLOCK), 0, s,
+                           P1, patches, uitems, soff, (const T *)u_in, (const T *)scratch, (T *)u_out,
+                           (T *)bflux, dt_dev, sc);
+        return (int)hipGetLastError();
+    }
+    const int e = P1.periodic ? 0 : 1;
+    const int64_t nbox = (int64_t)(P1.nx + 2 * e) * (P1.ny + 2 * e) * (P1.nz + 2 * e);
+    const int64_t ncell = (int64_t)P1.nx * P1.ny * P1.nz;
+    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, false>),
+                       dim3((unsigned)((nbox + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
+                       nullptr, nullptr, nullptr, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
+    hipLaunchKernelGGL((ppm_update_kernel<T, RS, false>),
+                       dim3((unsigned)((ncell + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
+                       nullptr, nullptr, nullptr, (const T *)u_in, (const T *)scratch, (T *)u_out,
+                       (T *)bflux, dt_dev, sc);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+int launch_ppm_d(int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
+                 const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+                 const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
+                 const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
+{
+#define GD_PPM(M, R) return launch_ppm_t<T, M, R>(P1, patches, pitems, npitems, uitems, nuitems, soff, \
+                                                  u_in, u_out, bflux, scratch, dt_dev, sc, hits, s)
+    const bool central = limiter == 4;
+    if (riemann == RS_HLL) {
+        if (central) GD_PPM(PPM_CENTRAL, RS_HLL);
+        GD_PPM(PPM_LIMITED, RS_HLL);
+    }
+    if (central) GD_PPM(PPM_CENTRAL, RS_HLLC);
+    GD_PPM(PPM_LIMITED, RS_HLLC);
+#undef GD_PPM
+}
+
+}  // namespace
+
+int64_t ppm_box_cells(const PatchDesc &P)
+{
+    const int e = P.periodic ? 0 : 1;
+    return (int64_t)(P.nx + 2 * e) * (P.ny + 2 * e) * (P.nz + 2 * e);
+}
+
+int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
+               const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+               const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
+               const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
+{
+    if (dtype == 1)
+        return launch_ppm_d<float>(limiter, riemann, P1, patches, pitems, npitems, uitems, nuitems,
+                                   soff, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
+    return launch_ppm_d<double>(limiter, riemann, P1, patches, pitems, npitems, uitems, nuitems,
+                                soff, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
+}
+
+}  // namespace gd

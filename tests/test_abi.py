@@ -192,3 +192,23 @@ def test_amr_calls_reject_a_null_plan(lib):
     assert lib.gd_amr_step(None, None, ctypes.byref(o), vp(16), vp(1 << 20), vp(1 << 24),
                            vp(1 << 26), vp(1 << 28), 1.4, 0.01, None, None) == -1
     assert lib.gd_amr_destroy(None) == 0
+
+
+def test_ppm_options_are_checked(lib):
+    """limiter 3 and 4 select the PPM reconstruction: a ghosted patch needs
+    three ghost layers, limiter 5 does not exist, and the adjoint, the MHD
+    step and the autotuner refuse PPM (GD_E_UNSUPPORTED) before anything else."""
+    assert _step(lib, _opts(limiter=3), ng=2) == -1
+    assert b"ng >= 3" in lib.gd_last_error(None)
+    assert _step(lib, _opts(limiter=4), ng=3) == -1          # valid: stops at the NULL ctx
+    assert b"ctx" in lib.gd_last_error(None)
+    assert _step(lib, _opts(limiter=5), ng=3) == -1
+    assert b"limiter" in lib.gd_last_error(None)
+    o = _opts(limiter=3, bc=1)
+    r = lib.godunov_step_adjoint(None, ctypes.byref(o), 4, 4, 4, 0, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(1 << 20), None, ctypes.c_void_p(1 << 24),
+                                 5 / 3, 0.1, 0.01, None)
+    assert r == -4
+    r = lib.godunov_step_mhd(None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000),
+                             ctypes.c_void_p(1 << 24), 5 / 3, 0.1, 0.01, None, 1.0, None, 0.1, None)
+    assert r == -4
