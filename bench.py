@@ -388,6 +388,44 @@ def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
                                 sum(stage_ms.values()), 4),
             "ghost_fill_gbs": round(fill_bytes / (stage_ms["ghost_fill"] * 1e-3) / 1e9, 1)}
 
+
+def bench_ppm(torch, gd, u0, steps=10, warmup=2):
+    """The 256^3 periodic box with the PPM reconstruction (limited parabola,
+    HLLC): per step one godunov_step_cfl (predict and update launches, then
+    the CFL reduction of the new state), dt in a device scalar."""
+    n = u0.shape[1]
+    log(f"bench: PPM, {n}^3 periodic box")
+    dx = 1.0 / n
+    a = torch.from_numpy(u0).cuda()
+    b = torch.empty_like(a)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one(src, dst):
+        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, limiter="ppm", out=dst, want_bflux=False,
+                cfl=0.5, dt_next=dt)
+
+    gd.cfl_dt(a, GAMMA, dx, 0.5, periodic=True, out=dt)
+    for i in range(warmup):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    a.copy_(torch.from_numpy(u0))
+    gd.cfl_dt(a, GAMMA, dx, 0.5, periodic=True, out=dt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = n ** 3
+    return {"workload": f"periodic Euler box {n}^3 FP64 (the turbulent box of the main line), "
+                        "PPM reconstruction (limited parabola) + Hancock half step + HLLC; per step "
+                        "one godunov_step_cfl (predict, update, CFL reduction), dt on the device",
+            "ms_per_step": round(ms, 4), "mcell_per_s": cells / (ms * 1e-3) / 1e6,
+            "bytes_per_step": 80 * cells, "achieved_gbs": 80 * cells / (ms * 1e-3) / 1e9,
+            "hbm_frac": 80 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
 def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
     5% amplitude), fixed dt: one adjoint step against one forward step, and
@@ -530,6 +568,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-ppm", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -599,6 +638,8 @@ def main():
         also["mhd"] = bench_mhd(torch, gd)
     if not args.no_amr:
         also["amr"] = bench_amr(torch, gd)
+    if not args.no_ppm:
+        also["ppm"] = bench_ppm(torch, gd, r["u0"])
     if not args.no_adjoint:
         also["adjoint"] = bench_adjoint(torch, gd)
     if also:

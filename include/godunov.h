@@ -122,7 +122,7 @@ int gd_reset_stats(gd_ctx *ctx);
 
 /* One Godunov step of one patch (steps 1-6 above; Sec. 3 and Sec. 4 of the
  * paper: all face fluxes of the patch computed on the device, boundary
- * fluxes returned). nx, ny, nz >= 1; ng >= 2 for GD_GHOSTED (ignored for
+ * fluxes returned). nx, ny, nz >= 1; ng >= 2 for GD_GHOSTED, ng >= 3 with PPM (ignored for
  * GD_PERIODIC). u_out must not overlap u_in. bflux may be NULL. If dt_dev is
  * not NULL the step reads dt (a double) from that device address, e.g. as
  * written by cfl_dt, and the dt argument is ignored. gamma > 1, dx > 0,
@@ -221,6 +221,31 @@ int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
  * the tiling, so outputs are bitwise identical across configurations. */
 int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int shape_batched,
                   int zpolicy_batched);
+
+/* ------------------------------------------------------------ PPM
+ *
+ * opts->limiter = GD_PPM or GD_PPM_UNLIMITED on godunov_step(_cfl) and
+ * godunov_step_batched(_cfl) replaces steps 2-4 of the scheme by the
+ * piecewise-parabolic reconstruction of Colella & Woodward (1984), the PPM
+ * the paper lists beside PLM and TVD (Sec. 2, Sec. 4). Per axis and primitive
+ * variable a of cell i:
+ *   interface value a_{i+1/2} = (a_i + a_{i+1})/2 - (da_{i+1} - da_i)/6,
+ *     da the MC-limited slope (GD_PPM) or the central difference
+ *     (a_{i+1} - a_{i-1})/2 (GD_PPM_UNLIMITED, fourth-order interface values);
+ *   edges a_L = a_{i-1/2}, a_R = a_{i+1/2}; GD_PPM then sets a_L = a_R = a_i
+ *     at a local extremum ((a_R - a_i)(a_i - a_L) <= 0), else with
+ *     D = a_R - a_L, m = a_i - (a_L + a_R)/2: a_L = 3a_i - 2a_R if
+ *     D m > D^2/6, a_R = 3a_i - 2a_L if D m < -D^2/6;
+ *   the Hancock half step of step 3 with slopes a_R - a_L, and the face
+ *     states W* + (a_R - W) (upper face) and W* + (a_L - W) (lower face),
+ *     floored; steps 5-7 unchanged.
+ * A ghosted patch needs ng >= 3 (GD_E_ARG otherwise): the stencil reads face
+ * ghosts to depth 3 and edge ghosts at depths (1, <= 2); corners never. The
+ * library keeps a device scratch of 30 values per cell of the patch's box
+ * extended by one layer (the periodic box itself), grown on first use (the
+ * growth synchronises the device). The _cfl entry points reduce the new
+ * state's CFL step in a separate launch after the step. The adjoint, the
+ * autotuner, the MHD step and the AMR seams return GD_E_UNSUPPORTED for PPM. */
 
 /* ------------------------------------------------------------ ideal MHD
  *
