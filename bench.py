@@ -426,6 +426,68 @@ def bench_ppm(torch, gd, u0, steps=10, warmup=2):
             "bytes_per_step": 80 * cells, "achieved_gbs": 80 * cells / (ms * 1e-3) / 1e9,
             "hbm_frac": 80 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
+
+def bench_streamed(torch, gd, steps=5, chunks=(64 << 20, 256 << 20)):
+    """The 4096-patch FP64 batch held in pinned host memory: one
+    godunov_step_batched_streamed per step (chunks copied in, stepped and
+    copied back on three streams, the copies overlapping the steps), against
+    the serial path (copy the whole batch in, one resident batched step, copy
+    it back) and the host<->device bandwidth of one large copy each way."""
+    from paper_1412_0934_amd import inputs
+    log("bench: streamed batch (pinned host memory)")
+    batch = bench_batched.cache
+    if batch is None:
+        batch = inputs.amr_batch(4096, seed=5)
+        bench_batched.cache = batch
+    dt = 1e-4
+    table = gd.patch_table(batch.dims, batch.ng, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, dt)
+    u_h = torch.from_numpy(batch.u_in).pin_memory()
+    out_h = torch.empty(batch.u_out_size, dtype=torch.float64).pin_memory()
+    fl_h = torch.empty(batch.flux_size, dtype=torch.float64).pin_memory()
+    u_d = torch.empty(len(batch.u_in), dtype=torch.float64, device="cuda")
+    out_d = torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda")
+    fl_d = torch.empty(batch.flux_size, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def serial():
+        u_d.copy_(u_h, non_blocking=True)
+        gd.step_batched(u_d, table, GAMMA, out=out_d, bflux=fl_d)
+        out_h.copy_(out_d, non_blocking=True)
+        fl_h.copy_(fl_d, non_blocking=True)
+
+    h2d_ms = timed(lambda: u_d.copy_(u_h, non_blocking=True), steps)
+    d2h_ms = timed(lambda: out_h.copy_(out_d, non_blocking=True), steps)
+    step_ms = timed(lambda: gd.step_batched(u_d, table, GAMMA, out=out_d, bflux=fl_d), steps)
+    serial_ms = timed(serial, steps)
+    cells = batch.interior_cells
+    res = {"workload": "the 4096-patch FP64 batch in pinned host memory, minmod + HLLC, bflux "
+                       "returned; per step one godunov_step_batched_streamed",
+           "h2d_gbs": round(u_h.numel() * 8 / (h2d_ms * 1e-3) / 1e9, 1),
+           "d2h_gbs": round(out_h.numel() * 8 / (d2h_ms * 1e-3) / 1e9, 1),
+           "resident_step_ms": round(step_ms, 3),
+           "serial_ms_per_step": round(serial_ms, 3),
+           "serial_mcell_per_s": cells / (serial_ms * 1e-3) / 1e6,
+           "streamed": []}
+    for chunk in chunks:
+        ms = timed(lambda: gd.step_batched_streamed(u_h, table, GAMMA, out=out_h, bflux=fl_h,
+                                                    chunk_bytes=chunk), steps)
+        res["streamed"].append({"chunk_bytes": chunk, "ms_per_step": round(ms, 3),
+                                "mcell_per_s": cells / (ms * 1e-3) / 1e6,
+                                "speedup_over_serial": round(serial_ms / ms, 3)})
+    return res
+
 def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
     5% amplitude), fixed dt: one adjoint step against one forward step, and
@@ -569,6 +631,7 @@ def main():
     ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-ppm", action="store_true")
+    ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -640,6 +703,8 @@ def main():
         also["amr"] = bench_amr(torch, gd)
     if not args.no_ppm:
         also["ppm"] = bench_ppm(torch, gd, r["u0"])
+    if not args.no_streamed:
+        also["streamed"] = bench_streamed(torch, gd)
     if not args.no_adjoint:
         also["adjoint"] = bench_adjoint(torch, gd)
     if also:

@@ -54,6 +54,7 @@
 #ifndef GODUNOV_H
 #define GODUNOV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -221,6 +222,33 @@ int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
  * the tiling, so outputs are bitwise identical across configurations. */
 int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int shape_batched,
                   int zpolicy_batched);
+
+/* ------------------------------------------------------------ streamed batches
+ *
+ * godunov_step_batched for a batch held in HOST memory (the paper's GPU ports
+ * copy each level's patches to the device and back every step, Sec. 3 and
+ * Sec. 4; Ramses could not hide that copy): u_in_host, u_out_host and
+ * bflux_host (may be NULL) are host buffers laid out as the device buffers of
+ * godunov_step_batched (same gd_patch offsets). The patches, taken in the
+ * order of their input offsets, are cut into chunks whose input, output and
+ * flux blocks fit chunk_bytes (>= 4096; a patch that alone exceeds it is
+ * GD_E_ARG). Each chunk is copied into one of two device staging slots,
+ * stepped there by the batched kernel and copied back, on three streams of
+ * the library's own, so that the copies of one chunk overlap the step of the
+ * next; consecutive blocks contiguous in host memory move in one copy.
+ * Results are bitwise those of godunov_step_batched on the same data.
+ * The pipeline starts after the work already queued on hip_stream, and
+ * hip_stream waits for its end: synchronise hip_stream before reading the
+ * host outputs; the host buffers must stay valid until then. Copies overlap
+ * only with pinned host memory (hipHostMalloc); pageable memory gives the
+ * same results without overlap. The context keeps the staging (two slots of
+ * up to chunk_bytes) and the chunk tables, rebuilt (synchronising the device)
+ * when the descriptors, dtype, chunk_bytes or batched tile choice change.
+ * GD_GHOSTED only; PLM limiters only (GD_E_UNSUPPORTED for PPM). */
+int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
+                                  const gd_patch *patches, const void *u_in_host, void *u_out_host,
+                                  void *bflux_host, const double *dt_dev, double gamma,
+                                  size_t chunk_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------ PPM
  *

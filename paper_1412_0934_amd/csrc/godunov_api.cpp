@@ -41,6 +41,9 @@ struct PpmCache {
 
 }  // namespace
 
+struct gd_stream_state;                  // the streamed-batch pipeline (below)
+static void free_stream_state(gd_stream_state *st);
+
 struct gd_ctx {
     int device = 0;
     int num_cus = 0;
@@ -59,6 +62,7 @@ struct gd_ctx {
     size_t ppm_bytes = 0;
     PpmCache ppm;                        // batch tables of the PPM step
     BatchCache ppm_cfl;                  // CFL tables over the PPM batch's outputs
+    gd_stream_state *stream = nullptr;   // streamed batches (created on first use)
     // tuned configuration per dtype (index 0: FP64, 1: FP32)
     int zlen_single[2] = { 32, 32 };
     int shape_single[2] = { gd::TILE_16x16, gd::TILE_16x16 };
@@ -340,6 +344,7 @@ int gd_destroy(gd_ctx *ctx)
     if (ctx->ppm.d_soff) (void)hipFree(ctx->ppm.d_soff);
     if (ctx->ppm_cfl.d_patches) (void)hipFree(ctx->ppm_cfl.d_patches);
     if (ctx->ppm_cfl.d_cfl_items) (void)hipFree(ctx->ppm_cfl.d_cfl_items);
+    free_stream_state(ctx->stream);
     if (ctx->d_u64) (void)hipFree(ctx->d_u64);
     if (ctx->d_u32) (void)hipFree(ctx->d_u32);
     delete ctx;
@@ -1258,6 +1263,293 @@ int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void
         return r;
     return amr_seam_impl(ctx, plan, &o, coarse_in, coarse_out, fine_out_base, fine_flux_base,
                          gamma, 0.0, dtp, s);
+}
+
+}  // extern "C"
+
+
+// ------------------------------------------------------------ streamed batches
+
+namespace {
+
+// One contiguous host <-> staging copy, in elements.
+struct CopyRun {
+    int64_t host, staging, elems;
+};
+
+struct StreamChunk {
+    int patch0, npatch;                 // range in the plan's descriptor table
+    int item0, nitems;                  // range in the plan's work items
+    int64_t in_elems, out_elems, fl_elems;
+    std::vector<CopyRun> in, out, flux;
+};
+
+}  // namespace
+
+// The plan of a streamed batch: chunks of patches that fit one staging slot,
+// the device descriptors and work items of every chunk (offsets relative to
+// the slot), and the pipeline's streams, events and staging memory.
+struct gd_stream_state {
+    std::vector<gd_patch> host;         // descriptors the plan was built from
+    int dtype = -1, shape = -1, zpolicy = -1, has_flux = -1;
+    size_t chunk_bytes = 0;
+    std::vector<StreamChunk> chunks;
+    int64_t in_max = 0, out_max = 0, fl_max = 0;        // slot regions, elements
+    gd::PatchDesc *d_patches = nullptr;
+    gd::WorkItem *d_items = nullptr;
+    size_t cap_patches = 0, cap_items = 0;
+    void *staging = nullptr;            // two slots of in_max + out_max + fl_max elements
+    size_t staging_bytes = 0;
+    hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    hipEvent_t ev_in[2] = {}, ev_comp[2] = {}, ev_out[2] = {};
+    hipEvent_t ev_start = nullptr;       // the caller's stream at the call
+    bool streams = false;
+};
+
+static void free_stream_state(gd_stream_state *st)
+{
+    if (!st) return;
+    if (st->d_patches) (void)hipFree(st->d_patches);
+    if (st->d_items) (void)hipFree(st->d_items);
+    if (st->staging) (void)hipFree(st->staging);
+    if (st->streams) {
+        for (int b = 0; b < 2; ++b) {
+            (void)hipEventDestroy(st->ev_in[b]);
+            (void)hipEventDestroy(st->ev_comp[b]);
+            (void)hipEventDestroy(st->ev_out[b]);
+        }
+        (void)hipEventDestroy(st->ev_start);
+        (void)hipStreamDestroy(st->s_in);
+        (void)hipStreamDestroy(st->s_comp);
+        (void)hipStreamDestroy(st->s_out);
+    }
+    delete st;
+}
+
+namespace {
+
+// Maximal runs of consecutive blocks (in chunk order) that are contiguous in
+// host memory; staging blocks are packed in chunk order.
+void add_block(std::vector<CopyRun> &runs, int64_t host, int64_t staging, int64_t elems)
+{
+    if (!runs.empty() && runs.back().host + runs.back().elems == host &&
+        runs.back().staging + runs.back().elems == staging) {
+        runs.back().elems += elems;
+        return;
+    }
+    runs.push_back(CopyRun{ host, staging, elems });
+}
+
+int build_stream_plan(gd_ctx *ctx, gd_stream_state &st, const gd_opts *opts, int npatch,
+                      const gd_patch *patches, bool has_flux, size_t chunk_bytes, hipStream_t s)
+{
+    const int dtype = opts->dtype, shape = ctx->shape_batched[dtype], zp = ctx->zpolicy_batched[dtype];
+    if (st.dtype == dtype && st.shape == shape && st.zpolicy == zp && st.has_flux == (int)has_flux &&
+        st.chunk_bytes == chunk_bytes && (int)st.host.size() == npatch &&
+        std::memcmp(st.host.data(), patches, npatch * sizeof(gd_patch)) == 0)
+        return GD_OK;
+    const size_t es = elem_size(opts);
+    const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
+    // patches in host-memory order of their inputs, so that packed batches
+    // copy in one run per chunk and buffer
+    std::vector<int> order(npatch);
+    for (int i = 0; i < npatch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return patches[a].u_in_off < patches[b].u_in_off; });
+    std::vector<gd::PatchDesc> desc;
+    std::vector<gd::WorkItem> items;
+    std::vector<StreamChunk> chunks;
+    int64_t in_max = 0, out_max = 0, fl_max = 0;
+    size_t i = 0;
+    while (i < order.size()) {
+        StreamChunk c{};
+        c.patch0 = (int)desc.size();
+        c.item0 = (int)items.size();
+        while (i < order.size()) {
+            const gd_patch &p = patches[order[i]];
+            const int64_t ni = in_elems(p.nx, p.ny, p.nz, p.ng, false);
+            const int64_t no = 5LL * p.nx * p.ny * p.nz;
+            const int64_t nf = has_flux && p.flux_off >= 0 ? flux_elems(p.nx, p.ny, p.nz) : 0;
+            const size_t bytes = (size_t)(c.in_elems + ni + c.out_elems + no + c.fl_elems + nf) * es;
+            if (bytes > chunk_bytes) {
+                if (c.npatch == 0)
+                    return fail(ctx, GD_E_ARG, "patch %d needs %zu bytes, more than chunk_bytes %zu",
+                                order[i], (size_t)(ni + no + nf) * es, chunk_bytes);
+                break;
+            }
+            gd::PatchDesc d = to_desc(p, false);
+            d.in_off = c.in_elems;
+            d.out_off = c.out_elems;
+            d.flux_off = nf ? c.fl_elems : -1;
+            add_block(c.in, p.u_in_off, c.in_elems, ni);
+            add_block(c.out, p.u_out_off, c.out_elems, no);
+            if (nf) add_block(c.flux, p.flux_off, c.fl_elems, nf);
+            c.in_elems += ni;
+            c.out_elems += no;
+            c.fl_elems += nf;
+            const int pidx = (int)desc.size();
+            desc.push_back(d);
+            const int zl = batched_zlen(p.nz, zp);
+            for (int z0 = 0; z0 < p.nz; z0 += zl)
+                for (int y0 = 0; y0 < p.ny; y0 += TY)
+                    for (int x0 = 0; x0 < p.nx; x0 += TX) {
+                        gd::WorkItem w{};
+                        w.patch = pidx;
+                        w.x0 = (int16_t)x0; w.y0 = (int16_t)y0;
+                        w.z0 = (int16_t)z0; w.z1 = (int16_t)std::min(z0 + zl, p.nz);
+                        w.shape = (int16_t)shape;
+                        items.push_back(w);
+                    }
+            ++c.npatch;
+            ++i;
+        }
+        c.nitems = (int)items.size() - c.item0;
+        in_max = std::max(in_max, c.in_elems);
+        out_max = std::max(out_max, c.out_elems);
+        fl_max = std::max(fl_max, c.fl_elems);
+        chunks.push_back(std::move(c));
+    }
+    if (items.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many work items");
+    int r;
+    if ((r = ensure_capacity(ctx, &st.d_patches, &st.cap_patches, desc.size()))) return r;
+    if ((r = ensure_capacity(ctx, &st.d_items, &st.cap_items, items.size()))) return r;
+    const size_t need = 2 * (size_t)(in_max + out_max + fl_max) * es;
+    hipError_t e = hipDeviceSynchronize();         // tables and staging may be in use
+    if (e == hipSuccess && need > st.staging_bytes) {
+        if (st.staging) (void)hipFree(st.staging);
+        st.staging = nullptr;
+        st.staging_bytes = 0;
+        if (hipMalloc(&st.staging, need) != hipSuccess)
+            return fail(ctx, GD_E_NOMEM, "staging of %zu bytes", need);
+        st.staging_bytes = need;
+    }
+    if (e == hipSuccess) e = hipMemcpy(st.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st.d_items, items.data(), items.size() * sizeof(gd::WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of the streaming tables");
+    (void)s;
+    st.host.assign(patches, patches + npatch);
+    st.dtype = dtype; st.shape = shape; st.zpolicy = zp; st.has_flux = (int)has_flux;
+    st.chunk_bytes = chunk_bytes;
+    st.chunks = std::move(chunks);
+    st.in_max = in_max; st.out_max = out_max; st.fl_max = fl_max;
+    return GD_OK;
+}
+
+int ensure_streams(gd_ctx *ctx, gd_stream_state &st)
+{
+    if (st.streams) return GD_OK;
+    hipError_t e = hipStreamCreateWithFlags(&st.s_in, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.s_comp, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.s_out, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_start, hipEventDisableTiming);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipEventCreateWithFlags(&st.ev_in[b], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_comp[b], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_out[b], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "streaming streams and events");
+    // mark every slot free: record each event once on its (idle) stream
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipEventRecord(st.ev_comp[b], st.s_comp);
+        if (e == hipSuccess) e = hipEventRecord(st.ev_out[b], st.s_out);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "streaming events");
+    st.streams = true;
+    return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
+                                  const gd_patch *patches, const void *u_in_host, void *u_out_host,
+                                  void *bflux_host, const double *dt_dev, double gamma,
+                                  size_t chunk_bytes, void *hip_stream)
+{
+    int r;
+    if ((r = check_opts(ctx, opts))) return r;
+    if (opts->bc != GD_GHOSTED) return fail(ctx, GD_E_UNSUPPORTED, "batched calls take ghosted patches only");
+    if ((r = reject_ppm(ctx, opts, "the streamed batch"))) return r;
+    if ((r = validate_patches(ctx, npatch, patches, false))) return r;
+    if (!(gamma > 1.0)) return fail(ctx, GD_E_ARG, "gamma must be > 1");
+    if (!u_in_host || !u_out_host) return fail(ctx, GD_E_ARG, "u_in_host and u_out_host must not be NULL");
+    if (chunk_bytes < 4096) return fail(ctx, GD_E_ARG, "chunk_bytes must be >= 4096");
+    const size_t es = elem_size(opts);
+    int64_t in_end = 0, out_end = 0, fl_end = 0;
+    for (int i = 0; i < npatch; ++i) {
+        const gd_patch &p = patches[i];
+        in_end = std::max<int64_t>(in_end, p.u_in_off + in_elems(p.nx, p.ny, p.nz, p.ng, false));
+        out_end = std::max<int64_t>(out_end, p.u_out_off + 5LL * p.nx * p.ny * p.nz);
+        if (bflux_host && p.flux_off >= 0)
+            fl_end = std::max<int64_t>(fl_end, p.flux_off + flux_elems(p.nx, p.ny, p.nz));
+    }
+    if (overlap(u_in_host, in_end * es, u_out_host, out_end * es))
+        return fail(ctx, GD_E_ARG, "u_out_host range overlaps u_in_host range");
+    if (bflux_host && fl_end > 0 && (overlap(bflux_host, fl_end * es, u_in_host, in_end * es) ||
+                                     overlap(bflux_host, fl_end * es, u_out_host, out_end * es)))
+        return fail(ctx, GD_E_ARG, "bflux_host range overlaps u_in_host or u_out_host");
+    if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
+    if ((r = set_device(ctx))) return r;
+    if (!ctx->stream) ctx->stream = new gd_stream_state();
+    gd_stream_state &st = *ctx->stream;
+    hipStream_t caller = (hipStream_t)hip_stream;
+    if ((r = ensure_streams(ctx, st))) return r;
+    if ((r = build_stream_plan(ctx, st, opts, npatch, patches, bflux_host != nullptr, chunk_bytes,
+                               caller)))
+        return r;
+
+    // the pipeline starts after the caller's earlier work (dt_dev may come
+    // from it) and the caller's stream waits for its end
+    hipError_t e = hipEventRecord(st.ev_start, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st.s_in, st.ev_start, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st.s_comp, st.ev_start, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "streamed batch start");
+    const int64_t slot = st.in_max + st.out_max + st.fl_max;
+    const int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, st.shape,
+                                               ctx->device);
+    gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    gd::CflOut co{ 0.0, nullptr, ctx->d_u64 + 2, ctx->d_u32 + 3 };
+    const char *hin = (const char *)u_in_host;
+    char *hout = (char *)u_out_host, *hfl = (char *)bflux_host;
+    for (size_t c = 0; c < st.chunks.size() && e == hipSuccess; ++c) {
+        const StreamChunk &ch = st.chunks[c];
+        const int b = (int)(c & 1);
+        char *base = (char *)st.staging + (size_t)b * slot * es;
+        char *sin = base, *sout = base + st.in_max * es, *sfl = sout + st.out_max * es;
+        // inputs of chunk c overwrite slot b once chunk c-2's step has read it
+        e = hipStreamWaitEvent(st.s_in, st.ev_comp[b], 0);
+        for (const CopyRun &run : ch.in)
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sin + run.staging * es, hin + run.host * es, run.elems * es,
+                                   hipMemcpyHostToDevice, st.s_in);
+        if (e == hipSuccess) e = hipEventRecord(st.ev_in[b], st.s_in);
+        // the step writes slot b's outputs once chunk c-2's have been copied out
+        if (e == hipSuccess) e = hipStreamWaitEvent(st.s_comp, st.ev_in[b], 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st.s_comp, st.ev_out[b], 0);
+        if (e == hipSuccess) {
+            int grid = std::max(1, std::min(ch.nitems, per_cu * ctx->num_cus));
+            int ke = gd::launch_step_batched(opts->dtype, opts->limiter, opts->riemann, st.shape,
+                                             st.d_patches, st.d_items + ch.item0, ch.nitems, sin, sout,
+                                             ch.fl_elems ? sfl : nullptr, dt_dev, sc, ctx->d_u64,
+                                             ctx->d_u32, grid, co, st.s_comp);
+            if (ke) e = (hipError_t)ke;
+        }
+        if (e == hipSuccess) e = hipEventRecord(st.ev_comp[b], st.s_comp);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st.s_out, st.ev_comp[b], 0);
+        for (const CopyRun &run : ch.out)
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hout + run.host * es, sout + run.staging * es, run.elems * es,
+                                   hipMemcpyDeviceToHost, st.s_out);
+        for (const CopyRun &run : ch.flux)
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hfl + run.host * es, sfl + run.staging * es, run.elems * es,
+                                   hipMemcpyDeviceToHost, st.s_out);
+        if (e == hipSuccess) e = hipEventRecord(st.ev_out[b], st.s_out);
+    }
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipStreamWaitEvent(caller, st.ev_out[b], 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "streamed batch");
+    return GD_OK;
 }
 
 }  // extern "C"

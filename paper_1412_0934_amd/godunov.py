@@ -8,6 +8,9 @@ or no GPU is present, the calls raise.
 Entry points (same names as the C ABI, see include/godunov.h):
     step(u, gamma, dx, dt)            one patch (ghosted or periodic)
     step_batched(...)                 many ghost-zoned patches, one launch
+    step_batched_streamed(...)        the same for a batch in host memory, streamed
+                                      through the device in chunks with copy/compute
+                                      overlap
     step_adjoint(u, lam_out, ...)     reverse mode of step for a fixed dt
     cfl_dt(u, gamma, dx, cfl)         CFL time step as a device scalar
     step_mhd(u, gamma, dx, dt, ch)    ideal-MHD step (HLLD + GLM) of a periodic box
@@ -77,7 +80,7 @@ EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset
            "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
            "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "godunov_step_mhd_cfl",
            "cfl_dt_mhd", "gd_amr_create", "gd_amr_destroy", "gd_amr_fill_ghosts", "gd_amr_reflux",
-           "gd_amr_step")
+           "gd_amr_step", "godunov_step_batched_streamed")
 
 _lib = None
 _lock = threading.Lock()
@@ -126,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.gd_amr_fill_ghosts.argtypes = [vp, vp, i32, vp, vp, vp]
         lib.gd_amr_reflux.argtypes = [vp, vp, P(gd_opts), vp, vp, vp, vp, dbl, dbl, vp, vp]
         lib.gd_amr_step.argtypes = [vp, vp, P(gd_opts), vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
+        lib.godunov_step_batched_streamed.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, vp, dbl,
+                                                      ctypes.c_size_t, vp]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -307,6 +312,44 @@ def step_batched(u_in, table, gamma, *, out, bflux=None, dt_dev=None, limiter="m
     ctx.check(ctx.lib.godunov_step_batched(ctx.handle, ctypes.byref(o), len(table),
                                            table.ctypes.data, _ptr(u_in), _ptr(out), _ptr(bflux),
                                            _ptr(dt_dev), float(gamma), _stream(stream)))
+    return out, bflux
+
+
+def step_batched_streamed(u_in, table, gamma, *, out, bflux=None, chunk_bytes=256 << 20,
+                          dt_dev=None, limiter="minmod", riemann="hllc", rho_floor=RHO_FLOOR,
+                          p_floor=P_FLOOR, stream=None, device=None):
+    """step_batched for a batch in host memory: u_in, out and bflux are CPU
+    tensors (pinned for copy/compute overlap) in the batched layout. The call
+    is asynchronous on the current (or given) stream: synchronise it before
+    reading out and bflux."""
+    for name, t in (("u_in", u_in), ("out", out), ("bflux", bflux)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.is_cuda:
+            raise TypeError(f"{name} must be a CPU tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.dtype != u_in.dtype:
+            raise TypeError(f"{name} must have dtype {u_in.dtype}")
+    if dt_dev is not None:
+        _check_tensor(dt_dev, "dt_dev", torch.float64)
+    table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    # the library cannot see the host buffers' sizes: check them here
+    d = np.stack([table["nx"], table["ny"], table["nz"]], axis=1).astype(np.int64)
+    g = 2 * table["ng"].astype(np.int64)[:, None]
+    need_in = int((table["u_in_off"] + 5 * np.prod(d + g, axis=1)).max()) if len(d) else 0
+    need_out = int((table["u_out_off"] + 5 * np.prod(d, axis=1)).max()) if len(d) else 0
+    fl = 10 * (d[:, 2] * d[:, 1] + d[:, 2] * d[:, 0] + d[:, 1] * d[:, 0])
+    has = table["flux_off"] >= 0
+    need_fl = int((table["flux_off"][has] + fl[has]).max()) if has.any() else 0
+    for name, t, need in (("u_in", u_in, need_in), ("out", out, need_out), ("bflux", bflux, need_fl)):
+        if t is not None and t.numel() < need:
+            raise ValueError(f"{name} holds {t.numel()} values, the patches need {need}")
+    ctx = context(device)
+    o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
+    ctx.check(ctx.lib.godunov_step_batched_streamed(
+        ctx.handle, ctypes.byref(o), len(table), table.ctypes.data, _ptr(u_in), _ptr(out),
+        _ptr(bflux), _ptr(dt_dev), float(gamma), int(chunk_bytes), _stream(stream)))
     return out, bflux
 
 

@@ -212,3 +212,22 @@ def test_ppm_options_are_checked(lib):
     r = lib.godunov_step_mhd(None, ctypes.byref(o), 4, 4, 4, ctypes.c_void_p(0x1000),
                              ctypes.c_void_p(1 << 24), 5 / 3, 0.1, 0.01, None, 1.0, None, 0.1, None)
     assert r == -4
+
+
+def test_streamed_batch_rejects_bad_arguments(lib):
+    from paper_1412_0934_amd import godunov
+    t = godunov.patch_table([[4, 4, 4], [6, 5, 4]], 2, [0, 2000], [0, 400], [0, 600], 1 / 64, 1e-3)
+    o = _opts()
+    vp = ctypes.c_void_p
+    args = lambda chunk, out=1 << 24, fl=None: (None, ctypes.byref(o), 2, t.ctypes.data, vp(1 << 20),
+                                               vp(out), fl, None, 5 / 3, chunk, None)
+    assert lib.godunov_step_batched_streamed(*args(1 << 20)) == -1          # NULL ctx
+    assert b"ctx" in lib.gd_last_error(None)
+    assert lib.godunov_step_batched_streamed(*args(1024)) == -1
+    assert b"chunk_bytes" in lib.gd_last_error(None)
+    assert lib.godunov_step_batched_streamed(*args(1 << 20, out=(1 << 20) + 64)) == -1
+    assert b"overlaps" in lib.gd_last_error(None)
+    o3 = _opts(limiter=3)
+    r = lib.godunov_step_batched_streamed(None, ctypes.byref(o3), 2, t.ctypes.data, vp(1 << 20),
+                                          vp(1 << 24), None, None, 5 / 3, 1 << 20, None)
+    assert r == -4
