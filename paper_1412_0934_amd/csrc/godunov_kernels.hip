@@ -156,8 +156,9 @@ __global__ __launch_bounds__(64) void cfl_finalize_kernel(double cfl, double *dt
 
 template <typename T, int TX, int TY>
 struct TileSmem {
-    // primitives of planes k-1 and k (buffer k & 1), two-deep x-y halo
-    T w[2][5][TY + 4][TX + 4];
+    // primitives of plane k with its two-deep x-y halo (the column's own
+    // planes k-1 and k+1 live in registers)
+    T w[5][TY + 4][TX + 4];
     // face states of the plane: x face i-1/2 of row j has its left state in
     // xl[.][j][i] and its right state in xr[.][j][i]; likewise y face j-1/2 of
     // column i in yl/yr[.][j][i]. The flux through a face overwrites its left
@@ -244,11 +245,11 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
     const int64_t ocol = (int64_t)gj * P.nx + gi;
 
     // ---- registers of the owned column
-    T W0[5], Wp[5], inv0 = T(1), invp = T(1);
+    T Wm[5], W0[5], Wp[5], inv0 = T(1), invp = T(1);
     T zprev[5], acc[5], zm[5], zpn[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        W0[q] = Wp[q] = T(0);
+        Wm[q] = W0[q] = Wp[q] = T(0);
         zprev[q] = acc[q] = zm[q] = zpn[q] = T(0);
     }
 
@@ -261,15 +262,13 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
 #pragma unroll
     for (int q = 0; q < 5; ++q) Upf[q] = Hpf[q] = Uold[q] = T(0);
 
-    // prologue: plane z0-2 (interior only, straight into its LDS buffer),
-    // plane z0-1 (into the column registers) and the loads of plane z0
+    // prologue: plane z0-2 (interior only, into W0, which the first step
+    // moves to Wm), plane z0-1 (into Wp) and the loads of plane z0
     if (owner) {
-        T U[5], Wt[5], inv;
+        T U[5], inv;
         if (interior) {
             load5(uin + view.plane(z0 - 2) + col, view.vstride, U);
-            prim_from_cons(U, Wt, inv, ph, hits);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) sm.w[(z0 - 2) & 1][q][cj + 2][ci + 2] = Wt[q];
+            prim_from_cons(U, W0, inv, ph, hits);
         }
         load5(uin + view.plane(z0 - 1) + col, view.vstride, U);
         prim_from_cons(U, Wp, invp, ph, hits);
@@ -282,11 +281,15 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
     for (int k = z0 - 1; k <= z1; ++k) {
         const bool pre = k < z0;
         const bool post = k == z1;
-        const int cur = k & 1, prv = (k - 1) & 1;
 
-        // ---- A: advance the column, stage plane k
+        // ---- A: advance the column, stage plane k. Every thread has
+        // finished reading plane k-1 from LDS (phase B, then a barrier)
+        // before it is overwritten here.
 #pragma unroll
-        for (int q = 0; q < 5; ++q) W0[q] = Wp[q];
+        for (int q = 0; q < 5; ++q) {
+            Wm[q] = W0[q];
+            W0[q] = Wp[q];
+        }
         inv0 = invp;
         if (owner && k + 1 <= last_plane) {
             prim_from_cons(Upf, Wp, invp, ph, hits);
@@ -294,13 +297,13 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
         }
         if (owner) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) sm.w[cur][q][ly][lx] = W0[q];
+            for (int q = 0; q < 5; ++q) sm.w[q][ly][lx] = W0[q];
         }
         if (!pre && !post && halo) {
             T Wh[5], invh;
             prim_from_cons(Hpf, Wh, invh, ph, hits);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) sm.w[cur][q][hj + 2][hi + 2] = Wh[q];
+            for (int q = 0; q < 5; ++q) sm.w[q][hj + 2][hi + 2] = Wh[q];
             if (k + 1 < z1) load5(uin + view.plane(k + 1) + hcol, view.vstride, Hpf);
         }
         __syncthreads();
@@ -312,9 +315,9 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
                 T c = W0[q];
-                Sx[q] = limited_slope<LIM>(c - sm.w[cur][q][ly][lx - 1], sm.w[cur][q][ly][lx + 1] - c);
-                Sy[q] = limited_slope<LIM>(c - sm.w[cur][q][ly - 1][lx], sm.w[cur][q][ly + 1][lx] - c);
-                Sz[q] = limited_slope<LIM>(c - sm.w[prv][q][ly][lx], Wp[q] - c);
+                Sx[q] = limited_slope<LIM>(c - sm.w[q][ly][lx - 1], sm.w[q][ly][lx + 1] - c);
+                Sy[q] = limited_slope<LIM>(c - sm.w[q][ly - 1][lx], sm.w[q][ly + 1][lx] - c);
+                Sz[q] = limited_slope<LIM>(c - Wm[q], Wp[q] - c);
             }
             predictor(W0, inv0, Sx, Sy, Sz, lam, ph.gamma, Ws);
             if (pre) {
@@ -348,8 +351,6 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                     face_state(Ws, Sz, half, zpn, ph, hits);
                 }
             }
-            // the conserved state of plane k-1, completed in phase C2
-            if (interior && k > z0) load5(uin + view.plane(k - 1) + col, view.vstride, Uold);
         }
         if (!post) __syncthreads();
         if (pre) continue;
@@ -408,6 +409,9 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                 for (int q = 0; q < 5; ++q) sheet[q * szs + (int64_t)gj * P.nx + gi] = F[q];
             }
             if (k > z0) {
+                // loaded here rather than ahead: the registers a prefetch would
+                // hold keep the kernel within three waves per SIMD without spills
+                load5(uin + view.plane(k - 1) + col, view.vstride, Uold);
                 // U' = U - dt/dx (acc + F_z(k-1/2)), acc = div_xy(k-1) - F_z(k-3/2)
                 T *o = out + (int64_t)(k - 1) * P.nx * P.ny + ocol;
                 T Un[5];
