@@ -32,7 +32,8 @@ struct PpmCache {
     std::vector<gd_patch> host;
     int dtype = -1;
     gd::PatchDesc *d_patches = nullptr;
-    gd::PpmItem *d_pitems = nullptr, *d_uitems = nullptr;
+    gd::PpmTile *d_pitems = nullptr;
+    gd::PpmItem *d_uitems = nullptr;
     int64_t *d_soff = nullptr;
     int npitems = 0, nuitems = 0;
     int64_t scratch_elems = 0;
@@ -409,7 +410,8 @@ int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream
         std::memcmp(c.host.data(), patches, npatch * sizeof(gd_patch)) == 0)
         return GD_OK;
     std::vector<gd::PatchDesc> desc(npatch);
-    std::vector<gd::PpmItem> pit, uit;
+    std::vector<gd::PpmTile> pit;
+    std::vector<gd::PpmItem> uit;
     std::vector<int64_t> soff(npatch);
     int64_t off = 0;
     for (int i = 0; i < npatch; ++i) {
@@ -419,7 +421,12 @@ int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream
         const int64_t cells = (int64_t)patches[i].nx * patches[i].ny * patches[i].nz;
         if (box >= 0x7fffffffLL) return fail(ctx, GD_E_ARG, "patch %d too large for the PPM step", i);
         off += 30 * box;
-        for (int64_t a = 0; a < box; a += 256) pit.push_back(gd::PpmItem{ i, (int32_t)a });
+        const int e = 1, bx = patches[i].nx + 2 * e, by = patches[i].ny + 2 * e, bz = patches[i].nz + 2 * e;
+        for (int z0 = 0; z0 < bz; z0 += gd::PPM_ZRANGE)
+            for (int y0 = 0; y0 < by; y0 += gd::PPM_TILE)
+                for (int x0 = 0; x0 < bx; x0 += gd::PPM_TILE)
+                    pit.push_back(gd::PpmTile{ i, (int16_t)x0, (int16_t)y0, (int16_t)z0,
+                                               (int16_t)std::min(z0 + gd::PPM_ZRANGE, bz) });
         for (int64_t a = 0; a < cells; a += 256) uit.push_back(gd::PpmItem{ i, (int32_t)a });
     }
     if (pit.size() > 0x7fffffff || uit.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many PPM items");
@@ -430,7 +437,7 @@ int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream
     if ((r = ensure_capacity(ctx, &c.d_soff, &c.cap_soff, soff.size()))) return r;
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c.d_pitems, pit.data(), pit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.d_pitems, pit.data(), pit.size() * sizeof(gd::PpmTile), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_uitems, uit.data(), uit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_soff, soff.data(), soff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "upload of PPM tables");

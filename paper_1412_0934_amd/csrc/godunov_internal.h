@@ -170,11 +170,19 @@ int launch_amr_seam(int dtype, int limiter, int riemann, const AmrTables &t, con
 int launch_set_scalar(double *dst, double v, hipStream_t s);
 
 // Piecewise-parabolic reconstruction (godunov_ppm.hip). A batched launch takes
-// 256-cell pieces of each patch: of its scratch box for the predict kernel,
-// of its interior for the update kernel.
+// tiles of each patch's scratch box for the predict kernel and 256-cell
+// pieces of its interior for the update kernel.
 struct PpmItem {
     int32_t patch, start;
 };
+
+// A tile of the predict kernel: 16 x 16 columns of a patch's scratch box at
+// (x0, y0), planes [z0, z1) of the box.
+struct PpmTile {
+    int32_t patch;
+    int16_t x0, y0, z0, z1;
+};
+constexpr int PPM_TILE = 16, PPM_ZRANGE = 16;
 
 // Cells of a patch's PPM scratch box: the interior (periodic) or the interior
 // plus one layer (ghosted); the scratch holds 30 values per box cell.
@@ -184,7 +192,7 @@ int64_t ppm_box_cells(const PatchDesc &P);
 // nullptr the single patch P1 is stepped; else the batch described by the
 // device tables (soff: per-patch scratch offsets in elements).
 int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-               const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+               const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
                const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
                const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s);
 

@@ -11,16 +11,18 @@
 // states are W* + (a_R - W) on the upper face and W* + (a_L - W) on the lower.
 //
 // Two launches per step, over a scratch of 30 values per predicted cell:
-//   ppm_predict  one thread per cell whose face states some face needs (the
-//                interior and, for a ghosted patch, the face ghosts of depth
-//                1): per axis the five-cell stencil -> edges, then the
+//   ppm_predict  16 x 16 column tiles of the cells whose face states some
+//                face needs (the interior and, for a ghosted patch, the face
+//                ghosts of depth 1), marching in z: each plane converted to
+//                primitives once into LDS, the column's z neighbours in
+//                registers; per axis the five-cell stencil -> edges, then the
 //                predictor and the six floored face states, stored SoA;
 //   ppm_update   one thread per interior cell: its six face fluxes from the
 //                staged states (a face shared by two cells is evaluated by
 //                both from the same inputs, so both get the same bits), the
 //                update, the boundary-flux sheets.
 // Both run over one patch (the grid covers it) or a batch (each workgroup
-// takes a 256-cell piece of one patch from a host-built table).
+// takes a tile, or a 256-cell piece, of one patch from a host-built table).
 #include "godunov_cell.h"
 #include "godunov_internal.h"
 
@@ -134,77 +136,173 @@ __device__ __forceinline__ void count_hits(int hits, unsigned long long *counter
     if (hits) atomicAdd(counter, (unsigned long long)hits);
 }
 
+// Tiles of the predict kernel: PT x PT columns of the scratch box marching
+// through up to PZ planes; each plane of the tile and a two-deep x-y halo is
+// converted to primitives once and staged in LDS, and each column keeps the
+// primitives of planes k-2 .. k+2 in registers.
+constexpr int PT = PPM_TILE, PZ = PPM_ZRANGE, PLW = PT + 4;
+constexpr int PPM_HALO = PLW * PLW - PT * PT;          // 144 halo cells per plane
+
+template <typename T>
+struct PpmSmem {
+    T w[5][PLW][PLW];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_raw(const T *__restrict__ u, const Addr &A, int i, int j, int k,
+                                         T U[5])
+{
+    const int64_t o = A.at(i, j, k);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) U[q] = u[o + q * A.vs];
+}
+
 template <typename T, int MODE, bool BATCHED>
-__global__ __launch_bounds__(PPM_BLOCK) void ppm_predict_kernel(
-    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmItem *__restrict__ items,
+__global__ __launch_bounds__(PT * PT) void ppm_predict_kernel(
+    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmTile *__restrict__ tiles,
     const int64_t *__restrict__ soff, const T *__restrict__ u_base, T *__restrict__ scratch,
     const double *dt_dev, Scalars sc, unsigned long long *hits_ctr)
 {
+    __shared__ PpmSmem<T> sm;
     PatchDesc P;
-    int start;
+    int x0, y0, z0, z1;
     int64_t so = 0;
     if constexpr (BATCHED) {
-        const PpmItem it = items[blockIdx.x];
-        P = patches[it.patch];
-        start = it.start;
-        so = soff[it.patch];
+        const PpmTile t = tiles[blockIdx.x];
+        P = patches[t.patch];
+        x0 = t.x0; y0 = t.y0; z0 = t.z0; z1 = t.z1;
+        so = soff[t.patch];
     } else {
         P = P1;
-        start = blockIdx.x * PPM_BLOCK;
+        const Box Bq = make_box(P);
+        const int ntx = (Bq.bx + PT - 1) / PT, nty = (Bq.by + PT - 1) / PT;
+        const int b = blockIdx.x, tile = b % (ntx * nty), seg = b / (ntx * nty);
+        x0 = (tile % ntx) * PT;
+        y0 = (tile / ntx) * PT;
+        z0 = seg * PZ;
+        z1 = min(z0 + PZ, Bq.bz);
     }
     const Box B = make_box(P);
-    const int idx = start + (int)threadIdx.x;
-    if (idx >= B.n) return;
-    const int i = idx % B.bx - B.e, j = (idx / B.bx) % B.by - B.e, k = idx / (B.bx * B.by) - B.e;
-    if (!P.periodic) {
-        const int di = i < 0 ? -i : (i >= P.nx ? i - P.nx + 1 : 0);
-        const int dj = j < 0 ? -j : (j >= P.ny ? j - P.ny + 1 : 0);
-        const int dk = k < 0 ? -k : (k >= P.nz ? k - P.nz + 1 : 0);
-        if (di + dj + dk > 1) return;       // an edge or corner of the box: never needed
-    }
     const Addr A = make_addr(P);
     const T *__restrict__ u = u_base + P.in_off;
     const Phys<T> ph = make_phys<T>(sc);
     const double dt = dt_dev ? *dt_dev : P.dt;
     const T lam = T(dt / (2.0 * P.dx));
+    const int e = B.e;
     int hits = 0;
 
-    T W[5], inv;
-    load_prim(u, A, i, j, k, ph, W, inv, hits);
-    T aL[3][5], aR[3][5], S[3][5];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int di = d == 0, dj = d == 1, dk = d == 2;
-        T Wmm[5], Wm[5], Wp[5], Wpp[5], unused;
-        load_prim(u, A, i - 2 * di, j - 2 * dj, k - 2 * dk, ph, Wmm, unused, hits);
-        load_prim(u, A, i - di, j - dj, k - dk, ph, Wm, unused, hits);
-        load_prim(u, A, i + di, j + dj, k + dk, ph, Wp, unused, hits);
-        load_prim(u, A, i + 2 * di, j + 2 * dj, k + 2 * dk, ph, Wpp, unused, hits);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            ppm_edges<MODE>(Wmm[q], Wm[q], W[q], Wp[q], Wpp[q], aL[d][q], aR[d][q]);
-            S[d][q] = aR[d][q] - aL[d][q];
-        }
+    // this thread's column (box coordinates bi, bj) and halo cell
+    const int tid = threadIdx.x, ci = tid % PT, cj = tid / PT;
+    const int bi = x0 + ci, bj = y0 + cj;
+    // the stencils of the box's cells reach box coordinates -2 .. bx+1
+    const bool col_load = bi <= B.bx + 1 && bj <= B.by + 1;
+    int hx = 0, hy = 0;
+    if (tid < 2 * PLW) { hy = tid / PLW; hx = tid % PLW; }
+    else if (tid < 4 * PLW) { hy = PT + 2 + (tid - 2 * PLW) / PLW; hx = (tid - 2 * PLW) % PLW; }
+    else if (tid < PPM_HALO) {
+        const int r = tid - 4 * PLW, c = r & 3;
+        hy = 2 + (r >> 2);
+        hx = c < 2 ? c : PT + c;
     }
-    T Ws[5];
-    predictor(W, inv, S[0], S[1], S[2], lam, ph.gamma, Ws);
-    T *__restrict__ out = scratch + so + idx;
+    const int hbi = x0 + hx - 2, hbj = y0 + hy - 2;
+    const bool halo_load = tid < PPM_HALO && hbi <= B.bx + 1 && hbj <= B.by + 1;
+    bool predicted = bi < B.bx && bj < B.by;
+    if (!P.periodic) {
+        const int i = bi - e, j = bj - e;
+        const int di = i < 0 ? -i : (i >= P.nx ? i - P.nx + 1 : 0);
+        const int dj = j < 0 ? -j : (j >= P.ny ? j - P.ny + 1 : 0);
+        predicted = predicted && di + dj <= 1;
+    }
+
+    // z window of the column: planes zc-2 .. zc+2 of the current plane zc
+    T win[5][5], winv[5], Upf[5], Hpf[5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        T lo[5], hi[5];
+    for (int p = 0; p < 5; ++p) {
+        winv[p] = T(1);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            lo[q] = Ws[q] + (aL[d][q] - W[q]);
-            hi[q] = Ws[q] + (aR[d][q] - W[q]);
+        for (int q = 0; q < 5; ++q) win[p][q] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Upf[q] = Hpf[q] = T(0);
+    const int zc0 = z0 - e;
+    if (col_load) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            T U[5];
+            load_raw(u, A, bi - e, bj - e, zc0 - 2 + p, U);
+            prim_from_cons(U, win[p], winv[p], ph, hits);
         }
-        hits += (lo[0] < ph.rho_floor) + (lo[4] < ph.p_floor) + (hi[0] < ph.rho_floor) +
-                (hi[4] < ph.p_floor);
-        lo[0] = fmax(lo[0], ph.rho_floor); lo[4] = fmax(lo[4], ph.p_floor);
-        hi[0] = fmax(hi[0], ph.rho_floor); hi[4] = fmax(hi[4], ph.p_floor);
+        load_raw(u, A, bi - e, bj - e, zc0 + 2, Upf);
+    }
+    if (halo_load) load_raw(u, A, hbi - e, hbj - e, zc0, Hpf);
+
+    const int lx = ci + 2, ly = cj + 2;
+    for (int kb = z0; kb < z1; ++kb) {
+        const int zc = kb - e;
+        if (col_load) {
+            prim_from_cons(Upf, win[4], winv[4], ph, hits);
+            if (kb + 1 < z1) load_raw(u, A, bi - e, bj - e, zc + 3, Upf);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            out[(int64_t)((2 * d) * 5 + q) * B.n] = lo[q];
-            out[(int64_t)((2 * d + 1) * 5 + q) * B.n] = hi[q];
+            for (int q = 0; q < 5; ++q) sm.w[q][ly][lx] = win[2][q];
+        }
+        if (halo_load) {
+            T Wh[5], invh;
+            prim_from_cons(Hpf, Wh, invh, ph, hits);
+            if (kb + 1 < z1) load_raw(u, A, hbi - e, hbj - e, zc + 1, Hpf);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.w[q][hy][hx] = Wh[q];
+        }
+        __syncthreads();
+
+        bool out_here = predicted;
+        if (!P.periodic) {
+            const int dk = zc < 0 ? -zc : (zc >= P.nz ? zc - P.nz + 1 : 0);
+            const int i = bi - e, j = bj - e;
+            const int di = i < 0 ? -i : (i >= P.nx ? i - P.nx + 1 : 0);
+            const int dj = j < 0 ? -j : (j >= P.ny ? j - P.ny + 1 : 0);
+            out_here = out_here && di + dj + dk <= 1;
+        }
+        if (out_here) {
+            const T *W = win[2];
+            T aL[3][5], aR[3][5], S[3][5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                ppm_edges<MODE>(sm.w[q][ly][lx - 2], sm.w[q][ly][lx - 1], W[q], sm.w[q][ly][lx + 1],
+                                sm.w[q][ly][lx + 2], aL[0][q], aR[0][q]);
+                ppm_edges<MODE>(sm.w[q][ly - 2][lx], sm.w[q][ly - 1][lx], W[q], sm.w[q][ly + 1][lx],
+                                sm.w[q][ly + 2][lx], aL[1][q], aR[1][q]);
+                ppm_edges<MODE>(win[0][q], win[1][q], W[q], win[3][q], win[4][q], aL[2][q], aR[2][q]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) S[d][q] = aR[d][q] - aL[d][q];
+            }
+            T Ws[5];
+            predictor(W, winv[2], S[0], S[1], S[2], lam, ph.gamma, Ws);
+            T *__restrict__ out = scratch + so + ((int64_t)kb * B.by + bj) * B.bx + bi;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                T lo[5], hi[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    lo[q] = Ws[q] + (aL[d][q] - W[q]);
+                    hi[q] = Ws[q] + (aR[d][q] - W[q]);
+                }
+                hits += (lo[0] < ph.rho_floor) + (lo[4] < ph.p_floor) + (hi[0] < ph.rho_floor) +
+                        (hi[4] < ph.p_floor);
+                lo[0] = fmax(lo[0], ph.rho_floor); lo[4] = fmax(lo[4], ph.p_floor);
+                hi[0] = fmax(hi[0], ph.rho_floor); hi[4] = fmax(hi[4], ph.p_floor);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    out[(int64_t)((2 * d) * 5 + q) * B.n] = lo[q];
+                    out[(int64_t)((2 * d + 1) * 5 + q) * B.n] = hi[q];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            winv[p] = winv[p + 1];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) win[p][q] = win[p + 1][q];
         }
     }
     count_hits(hits, hits_ctr);
@@ -300,14 +398,14 @@ __global__ __launch_bounds__(PPM_BLOCK) void ppm_update_kernel(
 }
 
 template <typename T, int MODE, int RS>
-int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmItem *pitems, int npitems,
+int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *pitems, int npitems,
                  const PpmItem *uitems, int nuitems, const int64_t *soff, const void *u_in,
                  void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
                  unsigned long long *hits, hipStream_t s)
 {
     if (patches) {
         if (npitems == 0 || nuitems == 0) return 0;
-        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, true>), dim3(npitems), dim3(PPM_BLOCK), 0, s,
+        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, true>), dim3(npitems), dim3(PT * PT), 0, s,
                            P1, patches, pitems, soff, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
         hipLaunchKernelGGL((ppm_update_kernel<T, RS, true>), dim3(nuitems), dim3(PPM_BLOCK), 0, s,
                            P1, patches, uitems, soff, (const T *)u_in, (const T *)scratch, (T *)u_out,
@@ -317,8 +415,10 @@ int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmItem *p
     const int e = P1.periodic ? 0 : 1;
     const int64_t nbox = (int64_t)(P1.nx + 2 * e) * (P1.ny + 2 * e) * (P1.nz + 2 * e);
     const int64_t ncell = (int64_t)P1.nx * P1.ny * P1.nz;
-    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, false>),
-                       dim3((unsigned)((nbox + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
+    const int64_t ntiles = (int64_t)((P1.nx + 2 * e + PT - 1) / PT) * ((P1.ny + 2 * e + PT - 1) / PT) *
+                           ((P1.nz + 2 * e + PZ - 1) / PZ);
+    (void)nbox;
+    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, false>), dim3((unsigned)ntiles), dim3(PT * PT), 0, s, P1,
                        nullptr, nullptr, nullptr, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
     hipLaunchKernelGGL((ppm_update_kernel<T, RS, false>),
                        dim3((unsigned)((ncell + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
@@ -329,7 +429,7 @@ int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmItem *p
 
 template <typename T>
 int launch_ppm_d(int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-                 const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+                 const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
                  const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
                  const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
 {
@@ -354,7 +454,7 @@ int64_t ppm_box_cells(const PatchDesc &P)
 }
 
 int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-               const PpmItem *pitems, int npitems, const PpmItem *uitems, int nuitems,
+               const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
                const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
                const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
 {
