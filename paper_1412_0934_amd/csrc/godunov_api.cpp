@@ -498,7 +498,8 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
     int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann,
                             ctx->shape_single[opts->dtype], P, u_in, u_out, bflux, dt_dev, sc,
-                            ctx->d_u64, ctx->zlen_single[opts->dtype], co, (hipStream_t)hip_stream);
+                            ctx->d_u64, ctx->zlen_single[opts->dtype], 4 * ctx->num_cus, co,
+                            (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "godunov_step launch");
     return GD_OK;
 }

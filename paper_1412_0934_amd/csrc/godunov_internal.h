@@ -50,10 +50,12 @@ struct CflOut {
 };
 
 // Launchers. Return 0 or a hipError_t value.
+// launch_step: z-ranges of zlen planes, shorter (down to two) where the
+// patch would otherwise give fewer than min_blocks workgroups.
 int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,
-                const Scalars &sc, unsigned long long *hits, int zlen, const CflOut &co,
-                hipStream_t s);
+                const Scalars &sc, unsigned long long *hits, int zlen, int min_blocks,
+                const CflOut &co, hipStream_t s);
 
 int launch_step_batched(int dtype, int limiter, int riemann, int shape,
                         const PatchDesc *d_patches, const WorkItem *d_items, int nitems,

@@ -593,9 +593,16 @@ __global__ __launch_bounds__(256) void cfl_single_kernel(PatchDesc P, const T *_
 template <typename T, int LIM, int RS, int TX, int TY>
 static int launch_step_t(const PatchDesc &P, const void *u_in, void *u_out, void *bflux,
                          const double *dt_dev, const Scalars &sc, unsigned long long *hits,
-                         int zlen, const CflOut &co, hipStream_t s)
+                         int zlen, int min_blocks, const CflOut &co, hipStream_t s)
 {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    if (ntiles * ((P.nz + zlen - 1) / zlen) < min_blocks) {
+        // too few workgroups to fill the chip: shorter z-ranges, down to two
+        // planes (a range recomputes the two planes below it)
+        const int64_t want = (min_blocks + ntiles - 1) / ntiles;
+        zlen = std::min<int64_t>(zlen, std::max<int64_t>(2, (P.nz + want - 1) / want));
+    }
     const int nseg = (P.nz + zlen - 1) / zlen;
     const int64_t nblocks = (int64_t)ntx * nty * nseg;
     if (nblocks <= 0 || nblocks > 0x7fffffff) return (int)hipErrorInvalidValue;
@@ -626,15 +633,15 @@ static int launch_batched_t(const PatchDesc *d_patches, const WorkItem *d_items,
 template <typename T, int LIM, int RS>
 static int dispatch_shape_step(int shape, const PatchDesc &P, const void *u_in, void *u_out,
                                void *bflux, const double *dt_dev, const Scalars &sc,
-                               unsigned long long *hits, int zlen, const CflOut &co,
-                               hipStream_t s)
+                               unsigned long long *hits, int zlen, int min_blocks,
+                               const CflOut &co, hipStream_t s)
 {
     switch (shape) {
-    case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
-    case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
-    case TILE_12x12: return launch_step_t<T, LIM, RS, 12, 12>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
-    case TILE_24x8: return launch_step_t<T, LIM, RS, 24, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
-    default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+    case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    case TILE_12x12: return launch_step_t<T, LIM, RS, 12, 12>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    case TILE_24x8: return launch_step_t<T, LIM, RS, 24, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
     }
 }
 
@@ -668,12 +675,12 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
 
 int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,
-                const Scalars &sc, unsigned long long *hits, int zlen, const CflOut &co,
-                hipStream_t s)
+                const Scalars &sc, unsigned long long *hits, int zlen, int min_blocks,
+                const CflOut &co, hipStream_t s)
 {
     if (dtype == 1)
-        GD_DISPATCH_SCHEME(dispatch_shape_step, float, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
-    GD_DISPATCH_SCHEME(dispatch_shape_step, double, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, co, s);
+        GD_DISPATCH_SCHEME(dispatch_shape_step, float, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    GD_DISPATCH_SCHEME(dispatch_shape_step, double, shape, P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
 }
 
 int launch_step_batched(int dtype, int limiter, int riemann, int shape,

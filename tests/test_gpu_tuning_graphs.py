@@ -35,13 +35,33 @@ def test_every_single_patch_configuration_gives_identical_bits(gd, dtype_name):
     results = []
     try:
         for shape in gd.TILE_SHAPES:
-            for zlen in (7, 16, 32, 64):
+            for zlen in (1, 2, 7, 32):
                 say("config", shape, zlen, dtype_name)
                 gd.set_config(dtype, shape_single=shape, zlen_single=zlen)
                 out, flux = gd.step(u, G, 1 / 64, dt)
                 results.append((host(out), host(flux)))
     finally:
         gd.set_config(dtype)
+    for out, flux in results[1:]:
+        assert np.array_equal(out, results[0][0]) and np.array_equal(flux, results[0][1])
+
+
+def test_z_ranges_on_a_wide_patch_give_identical_bits(gd):
+    """A patch wide enough that z-ranges of 3 and 8 planes keep their length
+    (a small patch is cut into two-plane ranges whatever the setting); 48
+    planes are cut to 16 by the four-workgroups-per-CU rule."""
+    import torch
+    u = torch.from_numpy(inputs.random_patch(256, 256, 48, seed=43)).to("cuda")
+    results = []
+    try:
+        for shape in ("24x8", "16x16"):
+            for zlen in (3, 8, 16, 48):
+                say("wide config", shape, zlen)
+                gd.set_config(torch.float64, shape_single=shape, zlen_single=zlen)
+                out, flux = gd.step(u, G, 1 / 64, 1e-3)
+                results.append((host(out), host(flux)))
+    finally:
+        gd.set_config(torch.float64)
     for out, flux in results[1:]:
         assert np.array_equal(out, results[0][0]) and np.array_equal(flux, results[0][1])
 
