@@ -488,6 +488,75 @@ def bench_streamed(torch, gd, steps=5, chunks=(64 << 20, 256 << 20)):
                                 "speedup_over_serial": round(serial_ms / ms, 3)})
     return res
 
+
+def bench_periodic_f32(torch, gd, u0, steps=10, warmup=2):
+    """The 256^3 periodic box in FP32 (the same values rounded once), tile
+    configuration autotuned for FP32, one godunov_step_cfl per step. Minimal
+    traffic 40 B per cell."""
+    n = u0.shape[1]
+    log(f"bench: FP32 {n}^3 periodic box")
+    dx = 1.0 / n
+    a = torch.from_numpy(u0).to("cuda", torch.float32)
+    b = torch.empty_like(a)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.autotune_step(a, GAMMA, dx, 0.5 * dx / 8.0, periodic=True, out=b)
+    stream = torch.cuda.current_stream()
+
+    def one(src, dst):
+        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, want_bflux=False, out=dst, cfl=0.5,
+                dt_next=dt)
+
+    gd.cfl_dt(a, GAMMA, dx, 0.5, periodic=True, out=dt)
+    for i in range(warmup):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    a.copy_(torch.from_numpy(u0))
+    gd.cfl_dt(a, GAMMA, dx, 0.5, periodic=True, out=dt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        one(a, b) if i % 2 == 0 else one(b, a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = n ** 3
+    return {"workload": f"the periodic {n}^3 turbulent box in FP32, minmod + HLLC, one "
+                        "godunov_step_cfl per step",
+            "config": gd.get_config(torch.float32), "ms_per_step": round(ms, 4),
+            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": 40 * cells,
+            "hbm_frac": 40 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_sod32(torch, gd, reps=200):
+    """The 32^3 Sod patch (2 ghost layers, outflow ghosts, 1% density noise):
+    the latency of one godunov_step call with boundary fluxes -- far below any
+    bandwidth limit (3.4 MB), so microseconds per call, not a roofline."""
+    import time
+    from paper_1412_0934_amd import inputs
+    log("bench: 32^3 Sod patch latency")
+    u, dx = inputs.sod_patch(32)
+    ud = torch.from_numpy(u).cuda()
+    out = torch.empty((5, 32, 32, 32), dtype=torch.float64, device="cuda")
+    fl = torch.empty(gd.bflux_size(32, 32, 32), dtype=torch.float64, device="cuda")
+    dt = gd.cfl_dt(ud, GAMMA, dx, 0.5)
+    for _ in range(10):
+        gd.step(ud, GAMMA, dx, dt_dev=dt, out=out, bflux=fl)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        gd.step(ud, GAMMA, dx, dt_dev=dt, out=out, bflux=fl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    return {"workload": "32^3 Sod patch + 2 ghost layers, FP64, minmod + HLLC, boundary fluxes, "
+                        "dt on the device; back-to-back godunov_step calls",
+            "us_per_call_gpu": round(e0.elapsed_time(e1) * 1e3 / reps, 2),
+            "us_per_call_host": round(wall * 1e6, 2),
+            "mcell_per_s": 32 ** 3 / (e0.elapsed_time(e1) * 1e-3 / reps) / 1e6}
+
 def bench_adjoint(torch, gd, steps=10, n=128, nsteps=20, every=5):
     """Adjoint cost on the 128^3 smooth periodic box (8 random Fourier modes,
     5% amplitude), fixed dt: one adjoint step against one forward step, and
@@ -632,6 +701,7 @@ def main():
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-ppm", action="store_true")
     ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -693,7 +763,9 @@ def main():
             "algorithmic_bytes_per_launch": r["bytes_per_launch"],
         },
     }
-    also = {}
+    also = {"sod32": bench_sod32(torch, gd)}
+    if not args.no_f32:
+        also["periodic_f32"] = bench_periodic_f32(torch, gd, r["u0"])
     if not args.no_batched:
         also["batched"] = [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
                            bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]
