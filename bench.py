@@ -702,6 +702,7 @@ def main():
     ap.add_argument("--no-ppm", action="store_true")
     ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-sod", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -763,7 +764,9 @@ def main():
             "algorithmic_bytes_per_launch": r["bytes_per_launch"],
         },
     }
-    also = {"sod32": bench_sod32(torch, gd)}
+    also = {}
+    if not args.no_sod:
+        also["sod32"] = bench_sod32(torch, gd)
     if not args.no_f32:
         also["periodic_f32"] = bench_periodic_f32(torch, gd, r["u0"])
     if not args.no_batched:
