@@ -496,10 +496,13 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
         return GD_OK;
     }
     gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
-    int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann,
-                            ctx->shape_single[opts->dtype], P, u_in, u_out, bflux, dt_dev, sc,
-                            ctx->d_u64, ctx->zlen_single[opts->dtype], 4 * ctx->num_cus, co,
-                            (hipStream_t)hip_stream);
+    // the workgroups the chip holds at once: fewer leave CUs idle
+    const int shape = ctx->shape_single[opts->dtype];
+    const int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, shape,
+                                               ctx->device);
+    int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann, shape, P, u_in, u_out,
+                            bflux, dt_dev, sc, ctx->d_u64, ctx->zlen_single[opts->dtype],
+                            per_cu * ctx->num_cus, co, (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "godunov_step launch");
     return GD_OK;
 }

@@ -88,6 +88,8 @@ int launch_adjoint(int limiter, int riemann, const PatchDesc &P, const double *u
                    const double *lam_out, const double *lam_bflux, double *lam_in,
                    const Scalars &sc, double dt, double *scratch, hipStream_t s);
 
+// Workgroups of the step kernel of a scheme and tile shape that one CU holds
+// at once (the batched and single-patch kernels have the same resources).
 int max_resident_blocks(int dtype, int limiter, int riemann, int shape, int device);
 
 // Ideal MHD on a periodic box (godunov_mhd.hip).
