@@ -59,6 +59,9 @@ def _step(lib, opts, nx=4, ny=4, nz=4, ng=2, u_in=0x1000, u_out=0x100000, bflux=
     ("bad riemann", dict(opts=dict(riemann=5))),
     ("negative floor", dict(opts=dict(rho_floor=-1.0))),
     ("ng < 2", dict(ng=1)),
+    ("ng > 64", dict(ng=65)),
+    ("extent above 16384", dict(nx=16385)),
+    ("z extent above 16384", dict(nz=16385)),
     ("zero extent", dict(nx=0)),
     ("gamma <= 1", dict(gamma=1.0)),
     ("dx <= 0", dict(dx=0.0)),

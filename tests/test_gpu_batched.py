@@ -51,6 +51,22 @@ def run_batched(gd, batch, dts, dtype, dt_dev=None, limiter="minmod", riemann="h
     return host(out), host(flux)
 
 
+def test_batch_with_maximum_extents(gd):
+    """Patches 16384 cells long along each axis among small ones: the 16-bit
+    tile coordinates of the work items at their last tile."""
+    import torch
+    dims = [(16384, 1, 1), (3, 4, 5), (1, 16384, 1), (2, 2, 2), (1, 1, 16384), (16384, 2, 3)]
+    states = [inputs.random_patch(*d, seed=70 + i) for i, d in enumerate(dims)]
+    batch = inputs.pack_batch(states, 2, 1 / 64, order_seed=4)
+    dts = np.array([0.4 * oracle.cfl_dt(s, G, 1 / 64) for s in states])
+    say("batch with maximum extents")
+    out, flux = run_batched(gd, batch, dts, torch.float64)
+    for p, u in enumerate(states):
+        ref, rflux, _ = oracle.step(u, G, 1 / 64, dts[p])
+        assert rel_norm_err(batch.patch_out(out, p), ref) <= 1e-12, p
+        assert rel_norm_err(batch.patch_flux(flux, p), rflux) <= 1e-12, p
+
+
 @pytest.mark.parametrize("lim,rs", [("minmod", "hllc"), ("mc", "hll"), ("none", "hllc")])
 def test_small_batch_matches_oracle_and_single_patch(gd, lim, rs):
     import torch

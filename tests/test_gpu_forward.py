@@ -74,6 +74,32 @@ def test_random_ghosted_patches(gd, shape, lim, rs):
     assert rel_norm_err(host(flux), rflux) <= TOL64
 
 
+@pytest.mark.parametrize("shape", [(16384, 1, 1), (1, 16384, 1), (1, 1, 16384), (16384, 3, 2)])
+def test_maximum_extents(gd, shape):
+    """Patches at the largest accepted extent (16384 cells along an axis):
+    the tile coordinates the kernels carry in 16 bits at their last tile,
+    and the one-column patch split into many short z-ranges."""
+    nx, ny, nz = shape
+    u = inputs.random_patch(nx, ny, nz, seed=nx + 3 * ny + 7 * nz)
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx)
+    ref, rflux, _ = oracle.step(u, G, dx, dt)
+    say("maximum extent", shape)
+    out, flux = gd.step(dev(u), G, dx, dt)
+    assert rel_norm_err(host(out), ref) <= TOL64
+    assert rel_norm_err(host(flux), rflux) <= TOL64
+
+
+def test_maximum_extents_periodic(gd):
+    u = inputs.random_patch(16384, 2, 1, seed=12)[:, 2:-2, 2:-2, 2:-2].copy()
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx, periodic=True)
+    ref, _, _ = oracle.step(u, G, dx, dt, periodic=True)
+    say("maximum extent periodic")
+    out, _ = gd.step(dev(u), G, dx, dt, periodic=True, want_bflux=False)
+    assert rel_norm_err(host(out), ref) <= TOL64
+
+
 @pytest.mark.parametrize("n", [8, 24, 40])
 @pytest.mark.parametrize("lim", ["minmod", "mc"])
 def test_periodic_box(gd, n, lim):

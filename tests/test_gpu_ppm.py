@@ -67,6 +67,20 @@ def test_periodic_box_matches_oracle(gd, shape, lim):
     assert rel_norm_err(host(b), bref) <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(16384, 1, 1), (1, 3, 16384)])
+def test_maximum_extents(gd, shape):
+    """The largest accepted extent along an axis: 16-bit tile coordinates of
+    the staged box (one layer wider than the interior) at their last tile."""
+    u = inputs.random_patch(*shape, ng=3, seed=sum(shape), generic=True)
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx, 0.4, ng=3)
+    ref, bref, _ = oracle.step(u, G, dx, dt, ng=3, limiter="ppm")
+    say("ppm maximum extent", shape)
+    out, b = gd.step(dev(u), G, dx, dt, ng=3, limiter="ppm")
+    assert rel_norm_err(host(out), ref) <= 1e-12
+    assert rel_norm_err(host(b), bref) <= 1e-12
+
+
 def test_fp32_matches_oracle(gd):
     import torch
     u = inputs.random_patch(12, 10, 9, ng=3, seed=5, generic=True)
