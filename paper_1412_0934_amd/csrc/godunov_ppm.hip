@@ -96,7 +96,7 @@ __device__ __forceinline__ T ppm_interface(T am, T a0, T ap, T app)
 {
     T d0 = ppm_slope<MODE>(am, a0, ap);
     T d1 = ppm_slope<MODE>(a0, ap, app);
-    return T(0.5) * (a0 + ap) - (d1 - d0) / T(6);
+    return T(0.5) * (a0 + ap) - div6(d1 - d0);
 }
 
 template <int MODE, typename T>
@@ -110,10 +110,11 @@ __device__ __forceinline__ void ppm_edges(T amm, T am, T a0, T ap, T app, T &aL,
             r = a0;
         } else {
             T D = r - l, m = a0 - T(0.5) * (l + r);
-            // the threshold is divided, not multiplied by 1/6, so that the
-            // branch matches the definition's rounding
-            if (D * m > D * D / T(6)) l = T(3) * a0 - T(2) * r;
-            else if (-(D * D) / T(6) > D * m) r = T(3) * a0 - T(2) * l;
+            // the threshold rounded as the division D^2 / 6 (and -(D^2) / 6 is
+            // its exact negative), so that the branch matches the definition
+            const T t = div6(D * D);
+            if (D * m > t) l = T(3) * a0 - T(2) * r;
+            else if (-t > D * m) r = T(3) * a0 - T(2) * l;
         }
     }
     aL = l;
