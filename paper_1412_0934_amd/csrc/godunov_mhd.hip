@@ -63,11 +63,27 @@ __device__ __forceinline__ T limited(int lim, T a, T b)
     return a > T(0) ? m : -m;
 }
 
+// sqrt(x), x >= 0, from the hardware reciprocal square root refined by one
+// Newton step (relative error within about 4e-15 in FP64)
 template <typename T>
+__device__ __forceinline__ T hw_sqrt(T x)
+{
+    return x > T(0) ? x * fast_rsqrt(x) : T(0);
+}
+
+// Divisions and square roots: EXACT = IEEE-rounded (the signal speeds behind
+// dt and ch), else the refined hardware estimates (the step's arithmetic).
+template <bool EXACT, typename T>
 __device__ __forceinline__ void to_prim(const Par<T> &P, const T U[NV], T W[NV])
 {
     T rho = U[0] < P.rho_floor ? P.rho_floor : U[0];
-    T u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+    T u, v, w;
+    if constexpr (EXACT) {
+        u = U[1] / rho; v = U[2] / rho; w = U[3] / rho;
+    } else {
+        const T ir = fast_rcp(rho);
+        u = U[1] * ir; v = U[2] * ir; w = U[3] * ir;
+    }
     T kin = T(0.5) * (U[1] * u + U[2] * v + U[3] * w);
     T mag = T(0.5) * (U[5] * U[5] + U[6] * U[6] + U[7] * U[7]);
     T p = P.gm1 * (U[4] - kin - mag);
@@ -89,16 +105,17 @@ __device__ __forceinline__ void to_cons(const Par<T> &P, const T W[NV], T U[NV])
 
 // fast magnetosonic speed of the primitive state along the axis whose field
 // component is bn
-template <typename T>
+template <bool EXACT, typename T>
 __device__ __forceinline__ T fast_speed(const Par<T> &P, const T W[NV], T bn)
 {
-    const T ir = T(1) / W[0];
+    const T ir = EXACT ? T(1) / W[0] : fast_rcp(W[0]);
     const T a2 = P.gamma * W[4] * ir;
     const T b2 = (W[5] * W[5] + W[6] * W[6] + W[7] * W[7]) * ir;
     const T s = a2 + b2;
     T disc = s * s - T(4) * a2 * (bn * bn * ir);
     disc = disc < T(0) ? T(0) : disc;
-    return sqrt(T(0.5) * (s + sqrt(disc)));
+    if constexpr (EXACT) return sqrt(T(0.5) * (s + sqrt(disc)));
+    else return hw_sqrt(T(0.5) * (s + hw_sqrt(disc)));
 }
 
 // physical GLM-MHD flux along axis D
@@ -147,7 +164,7 @@ __device__ __forceinline__ void hlld(const Par<T> &P, const T L[8], const T R[8]
         Fc[s][5] = u * By - v * Bn;
         Fc[s][6] = u * Bz - w * Bn;
         const T Wf[NV] = { rho, u, v, w, p, Bn, By, Bz, T(0) };
-        cf[s] = fast_speed(P, Wf, Bn);
+        cf[s] = fast_speed<false>(P, Wf, Bn);
     }
     const T SL = fmin(L[1] - cf[0], R[1] - cf[1]);
     const T SR = fmax(L[1] + cf[0], R[1] + cf[1]);
@@ -160,7 +177,7 @@ __device__ __forceinline__ void hlld(const Par<T> &P, const T L[8], const T R[8]
         return;
     }
     const T dL = (SL - L[1]) * L[0], dR = (SR - R[1]) * R[0];
-    const T idd = T(1) / (dR - dL);
+    const T idd = fast_rcp(dR - dL);
     const T SM = (dR * R[1] - dL * L[1] - pT[1] + pT[0]) * idd;
     const T pTs = (dR * pT[0] - dL * pT[1] + dL * dR * (R[1] - L[1])) * idd;
 
@@ -171,26 +188,28 @@ __device__ __forceinline__ void hlld(const Par<T> &P, const T L[8], const T R[8]
         const T *W = s ? R : L;
         const T S = s ? SR : SL;
         const T rho = W[0], u = W[1], v = W[2], w = W[3], By = W[6], Bz = W[7];
-        const T rs = rho * (S - u) / (S - SM);
+        const T isd = fast_rcp(S - SM);
+        const T rs = rho * (S - u) * isd;
         const T den = rho * (S - u) * (S - SM) - Bn * Bn;
         T vs = v, ws = w, Bys = By, Bzs = Bz;
         if (!(fabs(den) <= T(1e-12) * (rho * (S - u) * (S - u) + Bn * Bn))) {
-            const T t = Bn * (SM - u) / den;
+            const T iden = fast_rcp(den);
+            const T t = Bn * (SM - u) * iden;
             vs = v - By * t;
             ws = w - Bz * t;
-            const T q = (rho * (S - u) * (S - u) - Bn * Bn) / den;
+            const T q = (rho * (S - u) * (S - u) - Bn * Bn) * iden;
             Bys = By * q;
             Bzs = Bz * q;
         }
         const T uB = u * Bn + v * By + w * Bz;
         const T uBs = SM * Bn + vs * Bys + ws * Bzs;
-        const T Es = ((S - u) * Uc[s][4] - pT[s] * u + pTs * SM + Bn * (uB - uBs)) / (S - SM);
+        const T Es = ((S - u) * Uc[s][4] - pT[s] * u + pTs * SM + Bn * (uB - uBs)) * isd;
         Us[s][0] = rs; Us[s][1] = rs * SM; Us[s][2] = rs * vs; Us[s][3] = rs * ws;
         Us[s][4] = Es; Us[s][5] = Bn; Us[s][6] = Bys; Us[s][7] = Bzs;
-        sq[s] = sqrt(rs);
+        sq[s] = hw_sqrt(rs);
     }
-    const T SLs = SM - fabs(Bn) / sq[0];
-    const T SRs = SM + fabs(Bn) / sq[1];
+    const T SLs = SM - fabs(Bn) * fast_rcp(sq[0]);
+    const T SRs = SM + fabs(Bn) * fast_rcp(sq[1]);
     // the side of the contact the face lies on: left when SM >= 0 (values are
     // selected, not indexed, so that everything stays in registers)
     const bool left = SM >= T(0);
@@ -212,10 +231,11 @@ __device__ __forceinline__ void hlld(const Par<T> &P, const T L[8], const T R[8]
         return;
     }
     // between the Alfven waves: the double-star states
-    const T vL = Us[0][2] / Us[0][0], wL = Us[0][3] / Us[0][0];
-    const T vR = Us[1][2] / Us[1][0], wR = Us[1][3] / Us[1][0];
+    const T irL = fast_rcp(Us[0][0]), irR = fast_rcp(Us[1][0]);
+    const T vL = Us[0][2] * irL, wL = Us[0][3] * irL;
+    const T vR = Us[1][2] * irR, wR = Us[1][3] * irR;
     const T ByL = Us[0][6], BzL = Us[0][7], ByR = Us[1][6], BzR = Us[1][7];
-    const T iss = T(1) / (sq[0] + sq[1]);
+    const T iss = fast_rcp(sq[0] + sq[1]);
     const T vss = (sq[0] * vL + sq[1] * vR + (ByR - ByL) * sgn) * iss;
     const T wss = (sq[0] * wL + sq[1] * wR + (BzR - BzL) * sgn) * iss;
     const T Byss = (sq[0] * ByR + sq[1] * ByL + sq[0] * sq[1] * (vR - vL) * sgn) * iss;
@@ -241,7 +261,7 @@ template <int D, typename T>
 __device__ __forceinline__ void face_flux(const Par<T> &P, const T WL[NV], const T WR[NV], T F[NV])
 {
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-    const T Bns = T(0.5) * (WL[5 + D] + WR[5 + D]) - (WR[8] - WL[8]) / (T(2) * P.ch);
+    const T Bns = T(0.5) * (WL[5 + D] + WR[5 + D]) - (WR[8] - WL[8]) * fast_rcp(T(2) * P.ch);
     const T psis = T(0.5) * (WL[8] + WR[8]) - T(0.5) * P.ch * (WR[5 + D] - WL[5 + D]);
     const T L[8] = { WL[0], WL[1 + D], WL[1 + t1], WL[1 + t2], WL[4], Bns, WL[5 + t1], WL[5 + t2] };
     const T R[8] = { WR[0], WR[1 + D], WR[1 + t1], WR[1 + t2], WR[4], Bns, WR[5 + t1], WR[5 + t2] };
@@ -267,13 +287,13 @@ __device__ __forceinline__ int cell(int nx, int ny, int nz, int i, int j, int k)
     return (wrap(k, nz) * ny + wrap(j, ny)) * nx + wrap(i, nx);
 }
 
-template <typename T>
+template <bool EXACT, typename T>
 __device__ __forceinline__ void load_prim(const Par<T> &P, const T *__restrict__ u, int c, T W[NV])
 {
     T U[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) U[q] = u[q * P.n + c];
-    to_prim(P, U, W);
+    to_prim<EXACT>(P, U, W);
 }
 
 // face-state scratch: fs[(d*2 + side)*9 + q][cell], side 0 the upper-face
@@ -306,15 +326,15 @@ __global__ __launch_bounds__(256) void k_predict(Par<T> P, const T *__restrict__
     if (i >= P.nx || j >= P.ny) return;
     const int c = (k * P.ny + j) * P.nx + i;
     T W[NV], dU[NV], S[3][NV];
-    load_prim(P, u, c, W);
+    load_prim<false>(P, u, c, W);
 #pragma unroll
     for (int q = 0; q < NV; ++q) dU[q] = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         {
             T Wm[NV], Wp[NV];
-            load_prim(P, u, cell(P.nx, P.ny, P.nz, i - (d == 0), j - (d == 1), k - (d == 2)), Wm);
-            load_prim(P, u, cell(P.nx, P.ny, P.nz, i + (d == 0), j + (d == 1), k + (d == 2)), Wp);
+            load_prim<false>(P, u, cell(P.nx, P.ny, P.nz, i - (d == 0), j - (d == 1), k - (d == 2)), Wm);
+            load_prim<false>(P, u, cell(P.nx, P.ny, P.nz, i + (d == 0), j + (d == 1), k + (d == 2)), Wp);
 #pragma unroll
             for (int q = 0; q < NV; ++q) S[d][q] = limited<T>(LIM, W[q] - Wm[q], Wp[q] - W[q]);
         }
@@ -334,8 +354,8 @@ __global__ __launch_bounds__(256) void k_predict(Par<T> P, const T *__restrict__
         to_cons(P, dn, Ud);
 #pragma unroll
         for (int q = 0; q < NV; ++q) { Uu[q] += P.h * dU[q]; Ud[q] += P.h * dU[q]; }
-        to_prim(P, Uu, Wu);
-        to_prim(P, Ud, Wd);
+        to_prim<false>(P, Uu, Wu);
+        to_prim<false>(P, Ud, Wd);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             fs[(size_t)((d * 2 + 0) * NV + q) * P.n + c] = Wu[q];
@@ -418,8 +438,10 @@ __device__ __forceinline__ void sweep_pass(const Par<T> &P, const T *__restrict_
     __syncthreads();
 }
 
+// two waves per SIMD: the FP64 sweep sits at the 256-register limit
 template <typename T>
-__global__ __launch_bounds__(MT) void k_sweep(Par<T> P, const T *__restrict__ dyn,
+__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_sweep(Par<T> P, const T *__restrict__ dyn,
                                               const T *__restrict__ u, const T *__restrict__ fs,
                                               T *__restrict__ out, int ntx, int nty, int zlen,
                                               int nitem, int per_xcd,
@@ -471,11 +493,11 @@ __global__ __launch_bounds__(MT) void k_sweep(Par<T> P, const T *__restrict__ dy
             }
             if (acc) {
                 T W[NV];
-                to_prim(P, U, W);
+                to_prim<true>(P, U, W);
                 double sum = 0.0;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double v = (double)fabs(W[1 + d]) + (double)fast_speed(P, W, W[5 + d]);
+                    const double v = (double)fabs(W[1 + d]) + (double)fast_speed<true>(P, W, W[5 + d]);
                     sum += v;
                     dmax = fmax(dmax, v);
                 }
@@ -515,11 +537,11 @@ __global__ __launch_bounds__(256) void k_speeds(Par<T> P, const T *__restrict__ 
     double s = 0.0, m = 0.0;
     for (int c = blockIdx.x * 256 + threadIdx.x; c < P.n; c += gridDim.x * 256) {
         T W[NV];
-        load_prim(P, u, c, W);
+        load_prim<true>(P, u, c, W);
         double sum = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double v = (double)fabs(W[1 + d]) + (double)fast_speed(P, W, W[5 + d]);
+            const double v = (double)fabs(W[1 + d]) + (double)fast_speed<true>(P, W, W[5 + d]);
             sum += v;
             m = fmax(m, v);
         }
