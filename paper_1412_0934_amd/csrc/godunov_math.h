@@ -31,20 +31,4 @@ __device__ __forceinline__ double fast_rsqrt(double x)
 
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// x / 6 with the rounding of the division itself (x finite, not subnormal),
-// in three FMA-unit operations instead of the division sequence: x times the
-// rounded reciprocal y is a faithful quotient q, the remainder x - 6q is
-// exact in one FMA, and q + (x - 6q) y rounds to the correctly rounded
-// quotient (Markstein's theorem on FMA division); copysign gives a zero
-// quotient the sign of x. Checked against x / 6 on every binary32 value and
-// on 4e8 binary64 values.
-template <typename T>
-__device__ __forceinline__ T div6(T x)
-{
-    const T y = T(1) / T(6);
-    const T q = x * y;
-    const T r = fma(-q, T(6), x);
-    return copysign(fma(r, y, q), x);
-}
-
 }  // namespace gd
