@@ -234,3 +234,41 @@ def test_streamed_batch_rejects_bad_arguments(lib):
     r = lib.godunov_step_batched_streamed(None, ctypes.byref(o3), 2, t.ctypes.data, vp(1 << 20),
                                           vp(1 << 24), None, None, 5 / 3, 1 << 20, None)
     assert r == -4
+
+
+def _fresh_python(code):
+    import subprocess
+    import sys
+    return subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                          timeout=300)
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: without the built library the binding raises."""
+    r = _fresh_python("from paper_1412_0934_amd import godunov\n"
+                      "try:\n"
+                      "    godunov.load_library('/nonexistent/libgodunov.so')\n"
+                      "except RuntimeError as e:\n"
+                      "    print('raised:', e)\n")
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "not built" in r.stdout
+
+
+def test_step_without_a_gpu_raises():
+    """On a machine without a GPU the step raises instead of computing on the CPU."""
+    r = _fresh_python("import torch, numpy as np\n"
+                      "assert not torch.cuda.is_available()\n"
+                      "from paper_1412_0934_amd import godunov, inputs\n"
+                      "u = torch.from_numpy(inputs.random_patch(4, 4, 4))\n"
+                      "try:\n"
+                      "    godunov.step(u, 5 / 3, 0.1, 1e-3)\n"
+                      "except TypeError as e:\n"
+                      "    print('raised:', e)\n"
+                      "try:\n"
+                      "    godunov.context()\n"
+                      "except RuntimeError as e:\n"
+                      "    print('raised:', e)\n")
+    if "AssertionError" in r.stderr:
+        pytest.skip("a GPU is present")
+    assert r.returncode == 0, r.stderr
+    assert "must be a CUDA tensor" in r.stdout and "no CPU path" in r.stdout
