@@ -251,6 +251,58 @@ def test_ten_step_periodic_rollout_with_device_dt(gd):
     assert rel_norm_err(host(ud), ref) <= TOL64
 
 
+@pytest.fixture(scope="module")
+def box256():
+    """The periodic 256^3 Mach-2 box and the oracle's first two steps from it,
+    each with its own CFL dt (C = 0.5), and the dt after the second."""
+    n = 256
+    say("256^3 box and its oracle steps")
+    u0 = inputs.turbulent_box(n, mach=2.0)
+    dx = 1 / n
+    dts, states = [oracle.cfl_dt(u0, G, dx, 0.5, periodic=True)], [u0]
+    for _ in range(2):
+        states.append(oracle.step(states[-1], G, dx, dts[-1], periodic=True)[0])
+        dts.append(oracle.cfl_dt(states[-1], G, dx, 0.5, periodic=True))
+    return dx, states, dts
+
+
+@pytest.mark.parametrize("zlen", [16, 32])
+def test_full_box_256_in_the_timed_configuration(gd, box256, zlen):
+    """The box at full size, launched as the benchmark times it: 24x8 tiles,
+    godunov_step_cfl with dt read from and the next dt written to a device
+    scalar. Two consecutive steps, every cell against the oracle's, and the
+    three dts."""
+    import torch
+    dx, (u0, ref1, ref2), (dt0, dt1, dt2) = box256
+    try:
+        gd.set_config(torch.float64, shape_single="24x8", zlen_single=zlen)
+        say("256^3 full box, 24x8 /", zlen)
+        a = dev(u0)
+        b = torch.empty_like(a)
+        dt = gd.cfl_dt(a, G, dx, 0.5, periodic=True)
+        assert abs(float(host(dt)[0]) - dt0) <= 1e-14 * dt0
+        gd.step(a, G, dx, dt_dev=dt, periodic=True, want_bflux=False, out=b, cfl=0.5, dt_next=dt)
+        assert abs(float(host(dt)[0]) - dt1) <= 1e-14 * dt1
+        assert rel_norm_err(host(b), ref1) <= TOL64
+        gd.step(b, G, dx, dt_dev=dt, periodic=True, want_bflux=False, out=a, cfl=0.5, dt_next=dt)
+        assert abs(float(host(dt)[0]) - dt2) <= 1e-12 * dt2
+        assert rel_norm_err(host(a), ref2) <= TOL64
+    finally:
+        gd.set_config(torch.float64)
+
+
+def test_full_box_256_fp32(gd, box256):
+    """The same box in FP32 (inputs rounded once), one fused step, against the
+    FP64 oracle."""
+    import torch
+    dx, (u0, ref1, _), (dt0, _, _) = box256
+    say("256^3 full box fp32")
+    dt = torch.tensor([dt0], dtype=torch.float64, device="cuda")
+    out, _ = gd.step(dev(u0, torch.float32), G, dx, dt_dev=dt, periodic=True, want_bflux=False,
+                     cfl=0.5, dt_next=dt)
+    assert rel_norm_err(host(out), ref1) <= TOL32
+
+
 def test_fused_cfl_step_matches_separate_calls(gd):
     """godunov_step_cfl writes the same state as godunov_step and the same
     dt as cfl_dt on that state, bit for bit; dt_next may alias dt_dev."""
