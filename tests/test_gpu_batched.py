@@ -135,19 +135,25 @@ def amr():
     return inputs.amr_batch(4096, seed=5)
 
 
-@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
-def test_full_amr_batch(gd, amr, dtype_name):
-    """4096 patches 8^3..32^3 in one persistent launch, at the benchmark's
-    launch configuration: oracle parity on a seeded sample of patches, and the
-    boundary-flux telescoping identity on every patch."""
+@pytest.mark.parametrize("dtype_name,shape,policy", [("f64", "16x16", 1), ("f64", "24x8", 2),
+                                                     ("f32", "16x16", 1), ("f32", "24x8", 2)])
+def test_full_amr_batch(gd, amr, dtype_name, shape, policy):
+    """4096 patches 8^3..32^3 in one persistent launch, in the default
+    configuration and in the one the autotuner picks for this batch (24x8
+    tiles, whole-patch z-ranges): oracle parity on a seeded sample of
+    patches, and the boundary-flux telescoping identity on every patch."""
     import torch
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     tol = 1e-12 if dtype_name == "f64" else 1e-5
     rng = np.random.default_rng(77)
     sample = rng.choice(amr.npatch, size=48, replace=False)
     dt = 0.5 * min(amr.dx[p] / oracle.max_signal(amr.patch_in(p), G) for p in range(amr.npatch))
-    say("amr batch", dtype_name)
-    out, flux = run_batched(gd, amr, np.full(amr.npatch, dt), dtype)
+    say("amr batch", dtype_name, shape, policy)
+    try:
+        gd.set_config(dtype, shape_batched=shape, zpolicy_batched=policy)
+        out, flux = run_batched(gd, amr, np.full(amr.npatch, dt), dtype)
+    finally:
+        gd.set_config(dtype)
     assert np.all(np.isfinite(out)) and np.all(np.isfinite(flux))
     for p in sample:
         ref, rflux, _ = oracle.step(amr.patch_in(p), G, amr.dx[p], dt)
