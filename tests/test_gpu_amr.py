@@ -4,7 +4,9 @@ batched fine step, refluxing, averaging down) to 1e-12 in FP64 and 1e-5 in
 FP32 for every limiter / Riemann pair, the reflux launch alone, composite
 conservation, a uniform state, device dt, hierarchies with patches at the
 periodic boundary or spanning a whole axis, an empty hierarchy, and a 64^3
-box with 48 patches."""
+box with 48 patches; and the 128^3 box with 1024 patches the benchmark times,
+checked everywhere by the ghost fill and by conservation and on samples
+otherwise."""
 import math
 
 import numpy as np
@@ -191,3 +193,101 @@ def test_64_box_with_48_patches(gd):
     assert rel_norm_err(gfo, fo) <= 1e-12
     assert rel_norm_err(gff, ff) <= 1e-12
     assert rel_norm_err(gc, cn) <= 1e-12
+
+
+def test_full_size_hierarchy_sampled(gd):
+    """The two-level step at the size the benchmark times: a 128^3 periodic
+    coarse box with 1024 fine patches (gamma 5/3, seed 21). The whole oracle
+    step is too slow here (one coarse flux recomputed per interface face, in
+    Python), so: the ghost fill bit for bit everywhere; 64 sampled fine
+    patches against the oracle's step of their oracle-filled input; every
+    coarse cell away from the interfaces against the oracle's coarse step;
+    200 sampled uncovered interface cells against the oracle's coarse step
+    plus all their reflux corrections (coarse flux recomputed, fine fluxes
+    from the oracle's own fine steps); the covered cells of the sampled
+    patches against the average of the oracle's fine outputs; and composite
+    conservation over the whole hierarchy."""
+    import torch
+    import oracle
+    g = 5.0 / 3.0
+    h = inputs.amr_hierarchy(nc=128, nfine=1024, max_size=12, seed=21, gamma=g)
+    dt = oracle.cfl_dt(h.coarse, g, h.dx_coarse / 2, 0.5, periodic=True)
+    say("amr full size: gpu step")
+    plan = plan_for(gd, h)
+    ci = dev(h.coarse)
+    fi = dev(np.nan_to_num(h.fine.u_in, nan=-7.0))
+    co = torch.empty_like(ci)
+    fo = torch.full((h.fine.u_out_size,), float("nan"), dtype=ci.dtype, device="cuda")
+    ff = torch.full((h.fine.flux_size,), float("nan"), dtype=ci.dtype, device="cuda")
+    plan.step(ci, fi, g, dt, coarse_out=co, fine_out=fo, fine_flux=ff)
+    gc, gfi, gfo, gff = host(co), host(fi), host(fo), host(ff)
+    say("amr full size: ghost fill")
+    fin = amr.fill_ghosts(h, h.coarse)
+    assert np.array_equal(gfi, fin)
+
+    dxc = h.dx_coarse
+    npatch = len(h.lo)
+
+    def oracle_fine(p):
+        nx, ny, nz = (int(v) for v in h.n[p])
+        u = fin[h.fine.u_in_off[p]:h.fine.u_in_off[p] + 5 * (nx + 4) * (ny + 4) * (nz + 4)]
+        out, fl, _ = oracle.step(u.reshape(5, nz + 4, ny + 4, nx + 4), g, dxc / 2, dt)
+        flat = np.full(h.fine.flux_size, np.nan)
+        flat[h.fine.flux_off[p]:h.fine.flux_off[p] + fl.size] = fl
+        return out, flat
+
+    rng = np.random.default_rng(5)
+    say("amr full size: sampled fine patches and their covered cells")
+    for p in rng.choice(npatch, size=64, replace=False):
+        out, flat = oracle_fine(p)
+        assert rel_norm_err(h.fine.patch_out(gfo, p), out) <= 1e-12, p
+        assert rel_norm_err(h.fine.patch_flux(gff, p), h.fine.patch_flux(flat, p)) <= 1e-12, p
+        avg = np.zeros_like(h.coarse)
+        amr.average_down(_one_patch(h, p), out.ravel(), avg)
+        sx, sy, sz = (int(v) for v in h.n[p] // 2)
+        x, y, z = (int(v) for v in h.lo[p])
+        blk = (slice(None), slice(z, z + sz), slice(y, y + sy), slice(x, x + sx))
+        assert rel_norm_err(gc[blk], avg[blk]) <= 1e-12, p
+
+    say("amr full size: coarse cells")
+    cref = oracle.step(h.coarse, g, dxc, dt, periodic=True)[0]
+    faces = amr.interface_faces(h)
+    own = amr.owner_map(h).transpose(2, 1, 0)
+    touched = np.zeros(own.shape, dtype=bool)
+    by_cell = {}
+    for f in faces:
+        x, y, z = f[4]
+        touched[z, y, x] = True
+        by_cell.setdefault((x, y, z), []).append(f)
+    plain = (own < 0) & ~touched
+    for v in range(5):
+        scale = np.abs(cref[v]).max()
+        assert np.abs(gc[v][plain] - cref[v][plain]).max() <= 1e-12 * scale, v
+    cells = list(by_cell)
+    fine_flux = {}
+    for c in (cells[i] for i in rng.choice(len(cells), size=200, replace=False)):
+        want = cref[:, c[2], c[1], c[0]].copy()
+        for p, d, side, cell, out_cell in by_cell[c]:
+            if p not in fine_flux:
+                fine_flux[p] = oracle_fine(p)[1]
+            right = out_cell if side else cell
+            Fc = amr.coarse_face_flux(h.coarse, d, right, g, dxc, dt, "minmod", "hllc")
+            Ff = amr.fine_face_mean(h, fine_flux[p], p, d, side, cell)
+            want += dt / dxc * (Ff - Fc) if side else dt / dxc * (Fc - Ff)
+        scale = np.abs(cref).reshape(5, -1).max(axis=1)
+        assert np.all(np.abs(gc[:, c[2], c[1], c[0]] - want) <= 1e-12 * scale), c
+
+    say("amr full size: composite conservation")
+    t0, mag = _totals(h, h.coarse, lambda p: h.fine.patch_in(p)[:, 2:-2, 2:-2, 2:-2])
+    t1, _ = _totals(h, gc, lambda p: h.fine.patch_out(gfo, p))
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * mag), (t1 - t0) / mag
+
+
+def _one_patch(h, p):
+    """A view of hierarchy h restricted to patch p whose fine output buffer
+    is that patch's interior alone (for the oracle's averaging down)."""
+    import types
+    n = h.n[p]
+    fine = types.SimpleNamespace(patch_out=lambda buf, q: buf.reshape(5, int(n[2]), int(n[1]),
+                                                                      int(n[0])))
+    return types.SimpleNamespace(lo=[h.lo[p]], n=[n], fine=fine)
