@@ -152,7 +152,7 @@ def bench_periodic(torch, gd, steps, warmup, n=256, tile=None, zlen=None):
     }
 
 
-def bench_batched(torch, gd, steps, warmup, dtype_name):
+def bench_batched(torch, gd, steps, warmup, dtype_name, config=None, plain=True):
     import numpy as np
     from paper_1412_0934_amd import inputs
     log(f"bench: batched AMR workload ({dtype_name})")
@@ -169,7 +169,12 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
     flux = torch.empty(batch.flux_size, dtype=dtype, device="cuda")
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
     gd.cfl_dt_batched(u_in, table, GAMMA, 0.5, out=dt)
-    gd.autotune_batched(u_in, table, GAMMA, out=out, bflux=flux)
+    if config is None:
+        gd.autotune_batched(u_in, table, GAMMA, out=out, bflux=flux)
+    else:
+        cfg = gd.get_config(dtype)
+        cfg.update(shape_batched=config[0], zpolicy_batched=config[1])
+        gd.set_config(dtype, **cfg)
     log(f"bench: batched config {gd.get_config(dtype)}")
     # the batched step writes the batch's next CFL step into a second scalar
     # (the input state is the same every repetition, so dt stays the same)
@@ -202,7 +207,7 @@ def bench_batched(torch, gd, steps, warmup, dtype_name):
            "dtype": dtype_name, "cells": int(cells), "ms_per_step": ms,
            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
-    if dtype == torch.float64:
+    if dtype == torch.float64 and plain:
         res["plain"] = bench_plain(torch, gd, batch, u_in, out, flux, dt, cells, steps)
     return res
 
@@ -708,6 +713,10 @@ def main():
     ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-sod", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the 4096 separate launches of the batched leg")
+    ap.add_argument("--batched-config", default=None,
+                    help="SHAPE/POLICY for the batched leg instead of autotuning, e.g. 24x8/2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
@@ -775,8 +784,13 @@ def main():
     if not args.no_f32:
         also["periodic_f32"] = bench_periodic_f32(torch, gd, r["u0"])
     if not args.no_batched:
-        also["batched"] = [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64"),
-                           bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32")]
+        bcfg = None
+        if args.batched_config:
+            shape, pol = args.batched_config.split("/")
+            bcfg = (shape, int(pol))
+        also["batched"] = [bench_batched(torch, gd, max(5, args.steps // 2), 2, "f64", bcfg,
+                                         not args.no_plain),
+                           bench_batched(torch, gd, max(5, args.steps // 2), 2, "f32", bcfg)]
     if not args.no_mhd:
         also["mhd"] = bench_mhd(torch, gd)
     if not args.no_amr:
