@@ -719,7 +719,7 @@ def main():
                     help="SHAPE/POLICY for the batched leg instead of autotuning, e.g. 24x8/2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
-    ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "12x12", "24x8"], default=None,
+    ap.add_argument("--tile", choices=["16x16", "8x8", "32x8", "16x8", "24x8"], default=None,
                     help="fix the step kernel's tile shape instead of autotuning")
     ap.add_argument("--zlen", type=int, default=None, help="z-range length with --tile")
     args = ap.parse_args()

@@ -198,7 +198,7 @@ int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches
  * of a few launches per candidate), keeps the fastest in ctx for later calls
  * of the same dtype, and returns its index in *choice (may be NULL). The
  * outputs are overwritten; the stream is synchronised. Candidates: tiles of
- * 16x16, 32x8, 8x8, 12x12 and 24x8 interior columns; z-ranges of 16, 32 and
+ * 16x16, 32x8, 8x8, 16x8 and 24x8 interior columns; z-ranges of 16, 32 and
  * 64 planes (single patch) or of 8 planes, 16 planes and the whole patch
  * (batched). */
 int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
@@ -209,7 +209,7 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
                         void *hip_stream, int *choice);
 
 /* The configuration in use: tile shape index (0: 16x16, 1: 8x8, 2: 32x8,
- * 3: 12x12, 4: 24x8)
+ * 3: 16x8, 4: 24x8)
  * and z-range length (single patch) or z-range policy (batched: 0 = 8
  * planes, 1 = 16, 2 = whole patch) for dtype. */
 int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,

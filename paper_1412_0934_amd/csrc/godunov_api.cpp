@@ -745,7 +745,7 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
     if ((r = check_opts(ctx, opts))) return r;
     if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
     const int dt_i = opts->dtype;
-    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
+    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
                             gd::TILE_24x8 };
     const int zlens[3] = { 16, 32, 64 };
     const int keep_shape = ctx->shape_single[dt_i], keep_zlen = ctx->zlen_single[dt_i];
@@ -788,7 +788,7 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     if ((r = check_opts(ctx, opts))) return r;
     if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
     const int dt_i = opts->dtype;
-    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_12x12,
+    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
                             gd::TILE_24x8 };
     const int keep_shape = ctx->shape_batched[dt_i], keep_pol = ctx->zpolicy_batched[dt_i];
     // the same protocol as gd_autotune_step: a warm-up round, then the best

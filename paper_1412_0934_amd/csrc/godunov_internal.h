@@ -30,7 +30,7 @@ struct WorkItem {
 // Tile shapes the forward kernels are instantiated for (interior columns
 // TX x TY of one workgroup).
 enum TileShape : int {
-    TILE_16x16 = 0, TILE_8x8 = 1, TILE_32x8 = 2, TILE_12x12 = 3, TILE_24x8 = 4, NUM_TILE_SHAPES = 5
+    TILE_16x16 = 0, TILE_8x8 = 1, TILE_32x8 = 2, TILE_16x8 = 3, TILE_24x8 = 4, NUM_TILE_SHAPES = 5
 };
 int tile_tx(int shape);
 int tile_ty(int shape);

@@ -30,7 +30,7 @@ int tile_tx(int shape)
     switch (shape) {
     case TILE_8x8: return 8;
     case TILE_32x8: return 32;
-    case TILE_12x12: return 12;
+    case TILE_16x8: return 16;
     case TILE_24x8: return 24;
     default: return 16;
     }
@@ -38,14 +38,13 @@ int tile_tx(int shape)
 int tile_ty(int shape)
 {
     switch (shape) {
-    case TILE_8x8: case TILE_32x8: case TILE_24x8: return 8;
-    case TILE_12x12: return 12;
+    case TILE_8x8: case TILE_32x8: case TILE_16x8: case TILE_24x8: return 8;
     default: return 16;
     }
 }
 
 // Threads of a tile: TX*TY interior columns, then the 2(TX+TY) ring
-// columns, rounded up to whole waves (a 12x12 tile fills exactly 3 waves).
+// columns, rounded up to whole waves (24x8: 192 + 64 = 256 threads, 4 waves).
 constexpr int tile_threads(int tx, int ty) { return ((tx * ty + 2 * (tx + ty) + 63) / 64) * 64; }
 
 template <int TX, int TY>
@@ -639,7 +638,7 @@ static int dispatch_shape_step(int shape, const PatchDesc &P, const void *u_in, 
     switch (shape) {
     case TILE_8x8: return launch_step_t<T, LIM, RS, 8, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
     case TILE_32x8: return launch_step_t<T, LIM, RS, 32, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
-    case TILE_12x12: return launch_step_t<T, LIM, RS, 12, 12>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
+    case TILE_16x8: return launch_step_t<T, LIM, RS, 16, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
     case TILE_24x8: return launch_step_t<T, LIM, RS, 24, 8>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
     default: return launch_step_t<T, LIM, RS, 16, 16>(P, u_in, u_out, bflux, dt_dev, sc, hits, zlen, min_blocks, co, s);
     }
@@ -655,7 +654,7 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
     switch (shape) {
     case TILE_8x8: return launch_batched_t<T, LIM, RS, 8, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     case TILE_32x8: return launch_batched_t<T, LIM, RS, 32, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
-    case TILE_12x12: return launch_batched_t<T, LIM, RS, 12, 12>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    case TILE_16x8: return launch_batched_t<T, LIM, RS, 16, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     case TILE_24x8: return launch_batched_t<T, LIM, RS, 24, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     default: return launch_batched_t<T, LIM, RS, 16, 16>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     }
@@ -739,8 +738,8 @@ static int occupancy_t(int shape, int device)
     case TILE_32x8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 32, 8>, TileGeom<32, 8>::NT, 0);
         break;
-    case TILE_12x12:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 12, 12>, TileGeom<12, 12>::NT, 0);
+    case TILE_16x8:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 16, 8>, TileGeom<16, 8>::NT, 0);
         break;
     case TILE_24x8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 24, 8>, TileGeom<24, 8>::NT, 0);

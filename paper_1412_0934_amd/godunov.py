@@ -387,7 +387,7 @@ def step_adjoint(u, lam_out, gamma, dx, dt, *, lam_bflux=None, ng=2, periodic=Fa
     return out
 
 
-TILE_SHAPES = ("16x16", "8x8", "32x8", "12x12", "24x8")
+TILE_SHAPES = ("16x16", "8x8", "32x8", "16x8", "24x8")
 
 
 def autotune_step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", riemann="hllc",
