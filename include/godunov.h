@@ -219,7 +219,7 @@ int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
  * autotuning run). shape in [0, 4]; zlen_single in [1, 4096];
  * zpolicy_batched in {0, 1, 2}. zlen_single is an upper bound: a patch that
  * would give fewer workgroups than the device holds at once is cut into
- * shorter z-ranges (down to two planes). The choice never changes results: every
+ * shorter z-ranges (down to one plane). The choice never changes results: every
  * face flux and every update is evaluated by the same arithmetic whatever
  * the tiling, so outputs are bitwise identical across configurations. */
 int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int shape_batched,

@@ -50,7 +50,7 @@ struct CflOut {
 };
 
 // Launchers. Return 0 or a hipError_t value.
-// launch_step: z-ranges of zlen planes, shorter (down to two) where the
+// launch_step: z-ranges of zlen planes, shorter (down to one) where the
 // patch would otherwise give fewer than min_blocks workgroups.
 int launch_step(int dtype, int limiter, int riemann, int shape, const PatchDesc &P,
                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,

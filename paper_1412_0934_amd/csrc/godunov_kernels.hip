@@ -597,10 +597,11 @@ static int launch_step_t(const PatchDesc &P, const void *u_in, void *u_out, void
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     const int64_t ntiles = (int64_t)ntx * nty;
     if (ntiles * ((P.nz + zlen - 1) / zlen) < min_blocks) {
-        // too few workgroups to fill the chip: shorter z-ranges, down to two
-        // planes (a range recomputes the two planes below it)
+        // too few workgroups to fill the chip: shorter z-ranges, down to one
+        // plane (a range recomputes the two planes below it, which an
+        // otherwise idle chip absorbs)
         const int64_t want = (min_blocks + ntiles - 1) / ntiles;
-        zlen = std::min<int64_t>(zlen, std::max<int64_t>(2, (P.nz + want - 1) / want));
+        zlen = std::min<int64_t>(zlen, std::max<int64_t>(1, (P.nz + want - 1) / want));
     }
     const int nseg = (P.nz + zlen - 1) / zlen;
     const int64_t nblocks = (int64_t)ntx * nty * nseg;
