@@ -724,7 +724,7 @@ def main():
     ap.add_argument("--zlen", type=int, default=None, help="z-range length with --tile")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: the library runs on one GPU; multi-GPU runs are not implemented "
               "(the periodic box would shard as bricks with halo exchange)", file=sys.stderr)
         sys.exit(2)
 
