@@ -345,8 +345,11 @@ int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const v
  * dt on both levels:
  *   1. ghost fill: every ghost cell of a fine patch (both layers, corners
  *      included) takes the fine cell at the same place if a fine patch covers
- *      it, else the coarse cell containing it (piecewise-constant
- *      prolongation); positions wrap periodically;
+ *      it, else the limited linear prolongation of the coarse cell
+ *      containing it (per conserved variable, the coarse value plus a quarter
+ *      of the minmod slope along each axis, signed by the half of the coarse
+ *      cell the fine cell lies in; the eight children of a coarse cell
+ *      average back to it); positions wrap periodically;
  *   2. the coarse box and the fine patches each take one step (the fine
  *      batch with its boundary fluxes);
  *   3. refluxing: an uncovered coarse cell next to a fine patch had the

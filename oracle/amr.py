@@ -12,7 +12,11 @@ same dt on both levels:
 
 1. ghost fill: every ghost cell (two layers) of a fine patch takes the value of
    the fine cell at the same place if another fine patch covers it, else the
-   value of the coarse cell containing it (piecewise-constant prolongation);
+   limited linear prolongation of the coarse cell containing it: per conserved
+   variable, the coarse value plus a quarter of the minmod slope (undivided,
+   from the two periodic neighbours) along each axis, signed by the half of
+   the coarse cell the fine cell lies in -- the eight children of a coarse
+   cell average back to its value;
 2. the coarse box (periodic) and every fine patch take one Godunov step; the
    fine patches return their boundary fluxes;
 3. refluxing: a coarse cell outside the fine patches that shares a face with
@@ -42,6 +46,31 @@ def owner_map(h):
     return own
 
 
+def minmod(a, b):
+    """0 where a and b differ in sign or one is zero, else the one of smaller
+    magnitude."""
+    return np.where(a * b <= 0.0, 0.0, np.where(np.abs(a) <= np.abs(b), a, b))
+
+
+def prolong(coarse, gx, gy, gz):
+    """Value at fine cell (gx, gy, gz) of the limited linear prolongation of
+    its coarse parent (periodic box): U_c + ((sx Sx + sy Sy) + sz Sz) / 4 with
+    S_d the minmod slope of U along d and s_d = +1 in the parent's upper half
+    along d, -1 in its lower half."""
+    nc = coarse.shape[1]
+    cx, cy, cz = gx // 2, gy // 2, gz // 2
+    uc = coarse[:, cz, cy, cx]
+    slope = []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        lo = coarse[:, (cz - e[2]) % nc, (cy - e[1]) % nc, (cx - e[0]) % nc]
+        hi = coarse[:, (cz + e[2]) % nc, (cy + e[1]) % nc, (cx + e[0]) % nc]
+        slope.append(minmod(uc - lo, hi - uc))
+    sx, sy, sz = (slope[d] if g % 2 else -slope[d] for d, g in enumerate((gx, gy, gz)))
+    return uc + 0.25 * ((sx + sy) + sz)
+
+
 def fill_ghosts(h, coarse):
     """A copy of the fine input buffer with every ghost cell filled."""
     own = owner_map(h)
@@ -67,7 +96,7 @@ def fill_ghosts(h, coarse):
                                                   gy - 2 * h.lo[q][1] + 2,
                                                   gx - 2 * h.lo[q][0] + 2]
                     else:
-                        view[:, kk, jj, ii] = coarse[:, gz // 2, gy // 2, gx // 2]
+                        view[:, kk, jj, ii] = prolong(coarse, gx, gy, gz)
     return buf
 
 

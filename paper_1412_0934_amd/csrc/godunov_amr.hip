@@ -7,7 +7,8 @@
 // All three are gathers driven by tables the host builds once per hierarchy:
 //   fill     one thread per cell of a fine patch's ghosted box (interior
 //            cells return at once): the value of the fine cell at the same
-//            place if a fine patch covers it, else the coarse parent;
+//            place if a fine patch covers it, else the limited linear
+//            prolongation of the coarse parent;
 //   reflux   one thread per side of each coarse-fine face recomputes that
 //            side's predicted face state from the old coarse state (staged
 //            in the plan's scratch); then one thread per uncovered coarse
@@ -51,25 +52,46 @@ __global__ __launch_bounds__(FILL_BLOCK) void fill_kernel(AmrTables t, const T *
     const int fx = wrap(2 * P.lo[0] + ii - 2, 2 * t.nc[0]);
     const int fy = wrap(2 * P.lo[1] + jj - 2, 2 * t.nc[1]);
     const int fz = wrap(2 * P.lo[2] + kk - 2, 2 * t.nc[2]);
-    const int cidx = ((fz >> 1) * t.nc[1] + (fy >> 1)) * t.nc[0] + (fx >> 1);
+    const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;
+    const int cidx = (cz * t.nc[1] + cy) * t.nc[0] + cx;
     const int q = t.owner[cidx];
-    const T *src;
-    int64_t vs;
-    if (q >= 0) {
-        const AmrPatch Q = t.patches[q];
-        const int qx = Q.n[0] + 4, qy = Q.n[1] + 4;
-        const int li = fx - 2 * Q.lo[0] + 2, lj = fy - 2 * Q.lo[1] + 2, lk = fz - 2 * Q.lo[2] + 2;
-        src = fine + Q.in_off + ((int64_t)lk * qy + lj) * qx + li;
-        vs = (int64_t)qx * qy * (Q.n[2] + 4);
-    } else {
-        src = coarse + cidx;
-        vs = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
-    }
     T *dst = fine + P.in_off + idx;
     const int64_t dvs = box;
     T v[5];
+    if (q >= 0) {
+        // the fine cell of the patch covering this place
+        const AmrPatch Q = t.patches[q];
+        const int qx = Q.n[0] + 4, qy = Q.n[1] + 4;
+        const int li = fx - 2 * Q.lo[0] + 2, lj = fy - 2 * Q.lo[1] + 2, lk = fz - 2 * Q.lo[2] + 2;
+        const T *src = fine + Q.in_off + ((int64_t)lk * qy + lj) * qx + li;
+        const int64_t vs = (int64_t)qx * qy * (Q.n[2] + 4);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) v[c] = src[c * vs];
+        for (int c = 0; c < 5; ++c) v[c] = src[c * vs];
+    } else {
+        // limited linear prolongation of the coarse parent: per variable the
+        // minmod slope along each axis from the periodic neighbours, a
+        // quarter of it added with the sign of the parent's half the fine
+        // cell lies in; the eight children average back to the parent
+        const int nx = t.nc[0], ny = t.nc[1], nz = t.nc[2];
+        const int64_t vs = (int64_t)nx * ny * nz;
+        const int sx = nx, sy = nx * ny;
+        const int xm = cx > 0 ? -1 : nx - 1, xp = cx < nx - 1 ? 1 : 1 - nx;
+        const int ym = cy > 0 ? -sx : (ny - 1) * sx, yp = cy < ny - 1 ? sx : (1 - ny) * sx;
+        const int zm = cz > 0 ? -sy : (nz - 1) * sy, zp = cz < nz - 1 ? sy : (1 - nz) * sy;
+        const T *c0 = coarse + cidx;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T *u = c0 + c * vs;
+            const T uc = u[0];
+            T Sx = limited_slope<LIM_MINMOD>(uc - u[xm], u[xp] - uc);
+            T Sy = limited_slope<LIM_MINMOD>(uc - u[ym], u[yp] - uc);
+            T Sz = limited_slope<LIM_MINMOD>(uc - u[zm], u[zp] - uc);
+            Sx = (fx & 1) ? Sx : -Sx;
+            Sy = (fy & 1) ? Sy : -Sy;
+            Sz = (fz & 1) ? Sz : -Sz;
+            v[c] = uc + T(0.25) * ((Sx + Sy) + Sz);
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 5; ++c) dst[c * dvs] = v[c];
 }

@@ -76,14 +76,20 @@ def test_hierarchy_has_touching_patches_and_interfaces():
     assert touching >= 2
 
 
-def test_ghost_fill_takes_fine_cells_else_the_coarse_parent():
+def test_ghost_fill_takes_fine_cells_else_the_prolonged_coarse_parent():
+    """Coarse variables linear in x, y, z, one quadratic in x and one uniform:
+    a ghost cell over a fine patch takes that fine cell; any other takes its
+    parent plus a quarter of the smaller one-sided difference along each axis
+    -- for the linear fields the field at its own centre, g/2 - 1/4 in coarse
+    units (exact in binary) -- except where the parent sits on the periodic
+    seam, whose jump limits the slope to zero."""
     h = inputs.amr_hierarchy(gamma=G)
     nc = h.nc
     X = np.arange(nc, dtype=float)
     h.coarse[0] = X[None, None, :]
     h.coarse[1] = X[None, :, None]
     h.coarse[2] = X[:, None, None]
-    h.coarse[3] = -1.0
+    h.coarse[3] = (X * X)[None, None, :]
     h.coarse[4] = -1.0
     for p in range(len(h.lo)):
         nx, ny, nz = (int(v) for v in h.n[p])
@@ -112,11 +118,59 @@ def test_ghost_fill_takes_fine_cells_else_the_coarse_parent():
                     g = [(2 * h.lo[p][0] + ii - 2) % m, (2 * h.lo[p][1] + jj - 2) % m,
                          (2 * h.lo[p][2] + kk - 2) % m]
                     q = _covering_patch(h, [g[0] // 2, g[1] // 2, g[2] // 2])
+
+                    def lin(gi):
+                        c = gi // 2
+                        return float(c) if c in (0, nc - 1) else gi / 2 - 0.25
+
+                    def quad(gi):
+                        # x^2: one-sided differences 2c - 1 and 2c + 1, minmod the first
+                        c = gi // 2
+                        if c in (0, nc - 1):
+                            return float(c * c)
+                        return c * c + (0.25 if gi % 2 else -0.25) * (2 * c - 1)
+
                     want = ([g[0], g[1], g[2], 1.0, q] if q >= 0 else
-                            [g[0] // 2, g[1] // 2, g[2] // 2, -1.0, -1.0])
+                            [lin(g[0]), lin(g[1]), lin(g[2]), quad(g[0]), -1.0])
                     assert list(v[:, kk, jj, ii]) == want, (p, ii, jj, kk)
                     checked += 1
     assert checked > 1000
+
+
+def test_prolonged_children_average_to_their_parent():
+    """The eight children of an uncovered coarse cell, all ghost cells of the
+    patch beside it, average back to the coarse value (the slopes enter with
+    both signs), and each child differs from it by at most three quarters of
+    the largest slope magnitude allowed by its neighbours."""
+    h = inputs.amr_hierarchy(gamma=G, seed=17)
+    buf = amr.fill_ghosts(h, h.coarse)
+    own = amr.owner_map(h)
+    nc = h.nc
+    checked = 0
+    for p in range(len(h.lo)):
+        nx, ny, nz = (int(v) for v in h.n[p])
+        off = h.fine.u_in_off[p]
+        v = buf[off:off + 5 * (nx + 4) * (ny + 4) * (nz + 4)].reshape(5, nz + 4, ny + 4, nx + 4)
+        x = int(h.lo[p][0]) - 1                     # the coarse column beside the lower x face
+        if own[x % nc, h.lo[p][1], h.lo[p][2]] >= 0:
+            continue
+        for b in range(ny // 2):
+            for a in range(nz // 2):
+                y, z = int(h.lo[p][1]) + b, int(h.lo[p][2]) + a
+                if own[x % nc, y, z] >= 0:
+                    continue
+                kids = v[:, 2 + 2 * a:4 + 2 * a, 2 + 2 * b:4 + 2 * b, 0:2]
+                uc = h.coarse[:, z, y, x % nc]
+                scale = np.abs(h.coarse).reshape(5, -1).max(axis=1)
+                assert np.all(np.abs(kids.reshape(5, -1).mean(axis=1) - uc) <= 1e-15 * scale)
+                nb = [h.coarse[:, z, y, (x + dx) % nc] for dx in (-1, 1)] + \
+                     [h.coarse[:, z, (y + dy) % nc, x % nc] for dy in (-1, 1)] + \
+                     [h.coarse[:, (z + dz) % nc, y, x % nc] for dz in (-1, 1)]
+                smax = np.max(np.abs(np.array(nb) - uc), axis=0)
+                dev = np.abs(kids.reshape(5, -1) - uc[:, None]).max(axis=1)
+                assert np.all(dev <= 0.75 * smax + 1e-15 * scale)
+                checked += 1
+    assert checked > 0
 
 
 def test_uniform_state_is_unchanged_bit_for_bit():

@@ -73,8 +73,14 @@ MUTATIONS = [
     (AMR, "(blk[:, 1, 0] + blk[:, 1, 1])) * 0.25", "(blk[:, 1, 0] + blk[:, 1, 1])) * 0.5",
      "fine flux summed instead of averaged"),
     (AMR, "(z[0] + z[1]) * 0.125", "(z[0] + z[1]) * 0.25", "average down over four children"),
-    (AMR, "coarse[:, gz // 2, gy // 2, gx // 2]", "coarse[:, gy // 2, gz // 2, gx // 2]",
+    (AMR, "uc = coarse[:, cz, cy, cx]", "uc = coarse[:, cy, cz, cx]",
      "coarse parent with y and z swapped"),
+    (AMR, "return uc + 0.25 * ((sx + sy) + sz)", "return uc + 0.5 * ((sx + sy) + sz)",
+     "prolongation slope doubled"),
+    (AMR, "(slope[d] if g % 2 else -slope[d]", "(-slope[d] if g % 2 else slope[d]",
+     "prolongation slope with its sign reversed"),
+    (AMR, "np.where(np.abs(a) <= np.abs(b), a, b))", "np.where(np.abs(a) <= np.abs(b), b, a))",
+     "prolongation limiter taking the larger slope"),
     (AMR, "gx = (2 * h.lo[p][0] + ii - 2) % m", "gx = (2 * h.lo[p][0] + ii - 1) % m",
      "ghost position off by one"),
     (AMR, "gz - 2 * h.lo[q][2] + 2,", "gz - 2 * h.lo[q][2] + 1,", "fine source cell off by one"),
