@@ -5,10 +5,10 @@
 // the boundary fluxes that flux correction between levels needs).
 //
 // All three are gathers driven by tables the host builds once per hierarchy:
-//   fill     one thread per cell of a fine patch's ghosted box (interior
-//            cells return at once): the value of the fine cell at the same
-//            place if a fine patch covers it, else the limited linear
-//            prolongation of the coarse parent;
+//   fill     one thread per coarse cell of the shell around a fine patch
+//            (whose eight children are that patch's ghost cells): the
+//            children from the fine patch covering the shell cell, else the
+//            limited linear prolongation of the coarse cell;
 //   reflux   one thread per side of each coarse-fine face recomputes that
 //            side's predicted face state from the old coarse state (staged
 //            in the plan's scratch); then one thread per uncovered coarse
@@ -36,64 +36,78 @@ constexpr int SEAM_BLOCK = 128;
 // positions lie in [-2, 2 nc + 1) of a fine extent 2 nc >= 2)
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// One thread per cell of the one-coarse-cell shell around a patch (its two
+// fine ghost layers are exactly the eight children of each shell cell):
+// the eight children come from the fine patch covering the shell cell, or
+// from the limited linear prolongation of the coarse cell, whose slopes are
+// computed once for all eight.
 template <typename T>
 __global__ __launch_bounds__(FILL_BLOCK) void fill_kernel(AmrTables t, const T *__restrict__ coarse,
                                                           T *__restrict__ fine)
 {
     const AmrFillItem it = t.fill[blockIdx.x];
     const AmrPatch P = t.patches[it.patch];
-    const int gx = P.n[0] + 4, gy = P.n[1] + 4, gz = P.n[2] + 4;
-    const int box = gx * gy * gz;
+    const int sx = P.n[0] / 2 + 2, sy = P.n[1] / 2 + 2, sz = P.n[2] / 2 + 2;
     const int idx = it.start + (int)threadIdx.x;
-    if (idx >= box) return;
-    const int ii = idx % gx, jj = (idx / gx) % gy, kk = idx / (gx * gy);
-    if (ii >= 2 && ii < gx - 2 && jj >= 2 && jj < gy - 2 && kk >= 2 && kk < gz - 2) return;
-    // global fine cell, periodic over the fine extent of the coarse box
-    const int fx = wrap(2 * P.lo[0] + ii - 2, 2 * t.nc[0]);
-    const int fy = wrap(2 * P.lo[1] + jj - 2, 2 * t.nc[1]);
-    const int fz = wrap(2 * P.lo[2] + kk - 2, 2 * t.nc[2]);
-    const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;
-    const int cidx = (cz * t.nc[1] + cy) * t.nc[0] + cx;
+    if (idx >= sx * sy * sz) return;
+    const int ci = idx % sx, cj = (idx / sx) % sy, ck = idx / (sx * sy);
+    if (ci >= 1 && ci < sx - 1 && cj >= 1 && cj < sy - 1 && ck >= 1 && ck < sz - 1) return;
+    const int nx = t.nc[0], ny = t.nc[1], nz = t.nc[2];
+    // the shell cell, periodic over the coarse box
+    const int cx = wrap(P.lo[0] + ci - 1, nx), cy = wrap(P.lo[1] + cj - 1, ny);
+    const int cz = wrap(P.lo[2] + ck - 1, nz);
+    const int cidx = (cz * ny + cy) * nx + cx;
     const int q = t.owner[cidx];
-    T *dst = fine + P.in_off + idx;
-    const int64_t dvs = box;
-    T v[5];
+    const int gx = P.n[0] + 4, gy = P.n[1] + 4;
+    const int64_t dvs = (int64_t)gx * gy * (P.n[2] + 4);
+    // child (a, b, c) of the shell cell: ghost-box cell (2ci + a, 2cj + b, 2ck + c)
+    T *dst = fine + P.in_off + ((int64_t)(2 * ck) * gy + 2 * cj) * gx + 2 * ci;
     if (q >= 0) {
-        // the fine cell of the patch covering this place
+        // the fine patch covering the shell cell holds all eight children
         const AmrPatch Q = t.patches[q];
         const int qx = Q.n[0] + 4, qy = Q.n[1] + 4;
-        const int li = fx - 2 * Q.lo[0] + 2, lj = fy - 2 * Q.lo[1] + 2, lk = fz - 2 * Q.lo[2] + 2;
+        const int li = 2 * (cx - Q.lo[0]) + 2, lj = 2 * (cy - Q.lo[1]) + 2, lk = 2 * (cz - Q.lo[2]) + 2;
         const T *src = fine + Q.in_off + ((int64_t)lk * qy + lj) * qx + li;
         const int64_t vs = (int64_t)qx * qy * (Q.n[2] + 4);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) v[c] = src[c * vs];
-    } else {
-        // limited linear prolongation of the coarse parent: per variable the
-        // minmod slope along each axis from the periodic neighbours, a
-        // quarter of it added with the sign of the parent's half the fine
-        // cell lies in; the eight children average back to the parent
-        const int nx = t.nc[0], ny = t.nc[1], nz = t.nc[2];
-        const int64_t vs = (int64_t)nx * ny * nz;
-        const int sx = nx, sy = nx * ny;
-        const int xm = cx > 0 ? -1 : nx - 1, xp = cx < nx - 1 ? 1 : 1 - nx;
-        const int ym = cy > 0 ? -sx : (ny - 1) * sx, yp = cy < ny - 1 ? sx : (1 - ny) * sx;
-        const int zm = cz > 0 ? -sy : (nz - 1) * sy, zp = cz < nz - 1 ? sy : (1 - nz) * sy;
-        const T *c0 = coarse + cidx;
+        for (int c = 0; c < 5; ++c)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            const T *u = c0 + c * vs;
-            const T uc = u[0];
-            T Sx = limited_slope<LIM_MINMOD>(uc - u[xm], u[xp] - uc);
-            T Sy = limited_slope<LIM_MINMOD>(uc - u[ym], u[yp] - uc);
-            T Sz = limited_slope<LIM_MINMOD>(uc - u[zm], u[zp] - uc);
-            Sx = (fx & 1) ? Sx : -Sx;
-            Sy = (fy & 1) ? Sy : -Sy;
-            Sz = (fz & 1) ? Sz : -Sz;
-            v[c] = uc + T(0.25) * ((Sx + Sy) + Sz);
-        }
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        dst[c * dvs + ((int64_t)k * gy + j) * gx + i] =
+                            src[c * vs + ((int64_t)k * qy + j) * qx + i];
+        return;
     }
+    // limited linear prolongation: per variable the minmod slope along each
+    // axis from the periodic neighbours; a child adds a quarter of each with
+    // the sign of the half of the coarse cell it lies in, so the eight
+    // children average back to the coarse value
+    const int64_t vs = (int64_t)nx * ny * nz;
+    const int ox = nx, oy = nx * ny;
+    const int xm = cx > 0 ? -1 : nx - 1, xp = cx < nx - 1 ? 1 : 1 - nx;
+    const int ym = cy > 0 ? -ox : (ny - 1) * ox, yp = cy < ny - 1 ? ox : (1 - ny) * ox;
+    const int zm = cz > 0 ? -oy : (nz - 1) * oy, zp = cz < nz - 1 ? oy : (1 - nz) * oy;
+    const T *c0 = coarse + cidx;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) dst[c * dvs] = v[c];
+    for (int c = 0; c < 5; ++c) {
+        const T *u = c0 + c * vs;
+        const T uc = u[0];
+        const T Sx = limited_slope<LIM_MINMOD>(uc - u[xm], u[xp] - uc);
+        const T Sy = limited_slope<LIM_MINMOD>(uc - u[ym], u[yp] - uc);
+        const T Sz = limited_slope<LIM_MINMOD>(uc - u[zm], u[zp] - uc);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const T tx = i ? Sx : -Sx, ty = j ? Sy : -Sy, tz = k ? Sz : -Sz;
+                    dst[c * dvs + ((int64_t)k * gy + j) * gx + i] = uc + T(0.25) * ((tx + ty) + tz);
+                }
+    }
 }
 
 // Primitive state of coarse cell (x, y, z) of the periodic box.

@@ -1085,10 +1085,10 @@ int gd_amr_create(gd_ctx *ctx, int ncx, int ncy, int ncz, double dx_coarse, int 
         fl_end = std::max<int64_t>(fl_end, P.flux_off + flux_elems(P.n[0], P.n[1], P.n[2]));
     }
 
-    // ghost fill: 256-cell pieces of each ghosted box
+    // ghost fill: 256-cell pieces of each patch's one-coarse-cell shell box
     std::vector<gd::AmrFillItem> fill;
     for (int p = 0; p < npatch; ++p) {
-        const int box = (dp[p].n[0] + 4) * (dp[p].n[1] + 4) * (dp[p].n[2] + 4);
+        const int box = (dp[p].n[0] / 2 + 2) * (dp[p].n[1] / 2 + 2) * (dp[p].n[2] / 2 + 2);
         for (int s0 = 0; s0 < box; s0 += 256) fill.push_back(gd::AmrFillItem{ p, s0 });
     }
     // interface faces, per patch, axis, side and footprint cell; grouped by

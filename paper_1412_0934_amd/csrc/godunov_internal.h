@@ -124,7 +124,8 @@ struct AmrPatch {
     int64_t in_off, out_off, flux_off;
 };
 
-// 256 consecutive cells of one patch's ghosted box, for the ghost fill.
+// 256 consecutive cells of the box of coarse cells around one patch (the
+// patch's footprint and a one-cell shell), for the ghost fill.
 struct AmrFillItem {
     int32_t patch, start;
 };
