@@ -46,8 +46,12 @@
  * reported as errors; NaN inputs propagate to the outputs.
  *
  * Ordering: every call is asynchronous and stream-ordered on the HIP stream
- * passed in (NULL = the null stream); nothing synchronises the host except
- * gd_get_stats(). One gd_ctx per host thread. Calls that share a gd_ctx
+ * passed in (NULL = the null stream). The host waits only in gd_get_stats(),
+ * the autotuners, context and AMR-plan set-up, and the calls that (re)build
+ * device tables or grow the library's scratch: the first batched, PPM or CFL
+ * call with a new descriptor list and the first call that needs more
+ * scratch (each says so below); later calls with the same descriptors and
+ * sizes never wait. One gd_ctx per host thread. Calls that share a gd_ctx
  * share its device counters, so two of them in flight on different streams
  * at the same time race; serialise them on one stream.
  */
@@ -138,7 +142,8 @@ int godunov_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int n
  * patches that the paper's GPU ports build per level, Sec. 3 and Sec. 4).
  * patches is a HOST array of npatch descriptors (GD_GHOSTED layout only);
  * the library keeps a device copy and rebuilds it only when the descriptors
- * change, so repeated calls with the same descriptors allocate nothing and
+ * change (the rebuild synchronises hip_stream and uploads the tables), so
+ * repeated calls with the same descriptors allocate nothing, never wait and
  * may be captured into a HIP graph. If dt_dev is not NULL every patch uses
  * the device double *dt_dev instead of patches[i].dt. bflux_base may be
  * NULL (then every flux_off is ignored). Patches must not share output. */
