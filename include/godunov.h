@@ -51,9 +51,27 @@
  * device tables or grow the library's scratch: the first batched, PPM or CFL
  * call with a new descriptor list and the first call that needs more
  * scratch (each says so below); later calls with the same descriptors and
- * sizes never wait. One gd_ctx per host thread. Calls that share a gd_ctx
- * share its device counters, so two of them in flight on different streams
- * at the same time race; serialise them on one stream.
+ * sizes never wait. One gd_ctx per host thread.
+ *
+ * Streams: each stream a context sees (the first 64 distinct ones) gets
+ * device counters of its own -- the batched work queue and the CFL and MHD
+ * speed accumulators -- so steps, batched steps and CFL reductions in flight
+ * together on different streams do not interfere (beyond 64 streams the
+ * counter slots are shared round robin). The scratch memory of the adjoint,
+ * PPM and MHD steps and the cached batch tables are one per context: two
+ * calls of those kinds with different sizes or descriptors in flight
+ * together on different streams race; give each stream its own gd_ctx.
+ *
+ * Graph capture: a call made while hip_stream is capturing marks the tables
+ * and scratch it uses; the library never overwrites or frees marked memory
+ * before gd_destroy (a later call that needs other tables or more scratch
+ * allocates new ones), so a captured graph stays valid whatever calls
+ * follow. A call under capture that would have to build tables or grow
+ * scratch (it would wait on the host) returns GD_E_UNSUPPORTED: make one
+ * call with the same descriptors and sizes outside the capture first. The
+ * autotuners and the streamed batch cannot be captured (GD_E_UNSUPPORTED).
+ * A graph uses the counter slot of the stream it was captured on: replaying
+ * it while calls on that stream are in flight elsewhere races.
  */
 #ifndef GODUNOV_H
 #define GODUNOV_H
@@ -108,8 +126,8 @@ typedef struct {
     double dx, dt;          /* cell width and time step of this patch (levels may differ) */
 } gd_patch;
 
-/* Create a context on HIP device `device` (made current). Allocates a few
- * hundred bytes of device counters. Returns GD_E_HIP if there is no such
+/* Create a context on HIP device `device` (made current). Allocates about
+ * 5 KB of device counters (a floor-hit counter and 64 per-stream slots). Returns GD_E_HIP if there is no such
  * device; then *ctx is NULL and gd_last_error(NULL) has the reason. */
 int gd_create(gd_ctx **ctx, int device);
 

@@ -26,6 +26,7 @@ struct BatchCache {
     gd::CflItem *d_cfl_items = nullptr;
     int nitems = 0, ncfl = 0;
     size_t cap_patches = 0, cap_items = 0, cap_cfl = 0;
+    bool captured = false;            // a stream capture used these tables
 };
 
 struct PpmCache {
@@ -38,6 +39,26 @@ struct PpmCache {
     int npitems = 0, nuitems = 0;
     int64_t scratch_elems = 0;
     size_t cap_patches = 0, cap_pitems = 0, cap_uitems = 0, cap_soff = 0;
+    bool captured = false;
+};
+
+// Scratch memory grown on demand. A buffer that a stream capture used is
+// never freed before gd_destroy: a graph made from that capture still reads it.
+struct Scratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+    bool captured = false;
+};
+
+// Device counters of one stream: the batched work queue and the CFL and MHD
+// speed accumulators. Streams get slots of their own (up to NSLOT streams),
+// so launches in flight together on different streams do not share them.
+constexpr int NSLOT = 64;
+constexpr int SLOT_U64 = 8, SLOT_U32 = 4;
+struct Slot {
+    unsigned long long *u64;   // [1] cfl max bits, [2] fused cfl max bits,
+                               // [4..5] MHD speed maxima, [6..7] fused MHD maxima
+    unsigned *u32;             // [0..1] work queue, [2] cfl done, [3] fused cfl done
 };
 
 }  // namespace
@@ -49,18 +70,18 @@ struct gd_ctx {
     int device = 0;
     int num_cus = 0;
     std::string err;
-    // device counters: [0] floor hits, [1] cfl max bits, [2] fused cfl max
-    // bits, [4..5] MHD speed maxima, [6..7] fused MHD speed maxima
+    // device counters: d_u64[0] floor hits (summed by every stream), then
+    // NSLOT per-stream slots of SLOT_U64 words; d_u32: NSLOT slots of SLOT_U32
     unsigned long long *d_u64 = nullptr;
-    unsigned *d_u32 = nullptr;          // [0..1] work queue, [2] cfl done
+    unsigned *d_u32 = nullptr;
+    std::vector<hipStream_t> slot_stream;   // stream of each assigned slot
+    unsigned slot_shared = 0;               // round robin beyond NSLOT streams
     BatchCache batch;
     BatchCache cfl;                      // descriptor cache used by cfl_dt
-    double *d_adj = nullptr;             // adjoint scratch (grown on demand)
-    size_t adj_bytes = 0;
-    void *d_mhd = nullptr;               // MHD step scratch (grown on demand)
-    size_t mhd_bytes = 0;
-    void *d_ppm = nullptr;               // PPM face-state scratch (grown on demand)
-    size_t ppm_bytes = 0;
+    Scratch adj;                         // adjoint scratch (grown on demand)
+    Scratch mhd;                         // MHD step scratch (grown on demand)
+    Scratch ppm_s;                       // PPM face-state scratch (grown on demand)
+    std::vector<void *> retired;         // captured buffers replaced since; freed at destroy
     PpmCache ppm;                        // batch tables of the PPM step
     BatchCache ppm_cfl;                  // CFL tables over the PPM batch's outputs
     gd_stream_state *stream = nullptr;   // streamed batches (created on first use)
@@ -152,6 +173,87 @@ int check_scalars(gd_ctx *ctx, double gamma, double dx, double dt)
     return GD_OK;
 }
 
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// The counter slot of stream s (assigned on the stream's first call; host
+// bookkeeping only, so a first call under capture is fine).
+Slot slot_for(gd_ctx *ctx, hipStream_t s)
+{
+    int i = -1;
+    for (size_t k = 0; k < ctx->slot_stream.size(); ++k)
+        if (ctx->slot_stream[k] == s) { i = (int)k; break; }
+    if (i < 0) {
+        if ((int)ctx->slot_stream.size() < NSLOT) {
+            ctx->slot_stream.push_back(s);
+            i = (int)ctx->slot_stream.size() - 1;
+        } else {
+            i = (int)(ctx->slot_shared++ % NSLOT);
+        }
+    }
+    return Slot{ ctx->d_u64 + SLOT_U64 * (i + 1), ctx->d_u32 + SLOT_U32 * i };
+}
+
+// Free a device buffer that is being replaced, unless a capture used it.
+void release(gd_ctx *ctx, void *p, bool captured)
+{
+    if (!p) return;
+    if (captured) ctx->retired.push_back(p);
+    else (void)hipFree(p);
+}
+
+// Grow a scratch buffer to `need` bytes. The growth waits for the device
+// (work already queued may use the old buffer) and is refused under stream
+// capture; a call under capture marks the buffer as captured.
+int ensure_scratch(gd_ctx *ctx, Scratch &sc, size_t need, hipStream_t s, const char *what)
+{
+    const bool cap = capturing(s);
+    if (need > sc.bytes || !sc.p) {
+        if (cap)
+            return fail(ctx, GD_E_UNSUPPORTED,
+                        "%s scratch must grow (to %zu bytes), which a stream capture cannot do: "
+                        "make one call of this size outside the capture first", what, need);
+        hipError_t he = hipDeviceSynchronize();
+        if (he != hipSuccess) return hip_fail(ctx, he, what);
+        release(ctx, sc.p, sc.captured);
+        sc = Scratch{};
+        if (hipMalloc(&sc.p, need) != hipSuccess) {
+            sc.p = nullptr;
+            return fail(ctx, GD_E_NOMEM, "%s scratch of %zu bytes", what, need);
+        }
+        sc.bytes = need;
+    }
+    if (cap) sc.captured = true;
+    return GD_OK;
+}
+
+// A table cache that must be rebuilt: refused under capture; otherwise the
+// device waits (other streams may read the tables) and captured tables are
+// set aside rather than overwritten.
+int prepare_rebuild(gd_ctx *ctx, hipStream_t s, bool &captured, std::initializer_list<void **> ptrs,
+                    std::initializer_list<size_t *> caps, const char *what)
+{
+    if (capturing(s))
+        return fail(ctx, GD_E_UNSUPPORTED,
+                    "the %s for these descriptors are not built, which a stream capture cannot do: "
+                    "make one call with them outside the capture first", what);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    if (captured) {
+        for (void **p : ptrs) {
+            release(ctx, *p, true);
+            *p = nullptr;
+        }
+        for (size_t *c : caps) *c = 0;
+        captured = false;
+    }
+    return GD_OK;
+}
+
 template <typename X>
 int ensure_capacity(gd_ctx *ctx, X **ptr, size_t *cap, size_t n)
 {
@@ -216,7 +318,14 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
 {
     BatchCache &c = ctx->batch;
     const int tag = dtype * 16 + zpolicy;
-    if (c.dtype == tag && c.shape == shape && same_patches(c, npatch, patches)) return GD_OK;
+    if (c.dtype == tag && c.shape == shape && same_patches(c, npatch, patches)) {
+        if (capturing(s)) c.captured = true;
+        return GD_OK;
+    }
+    int r;
+    if ((r = prepare_rebuild(ctx, s, c.captured, { (void **)&c.d_patches, (void **)&c.d_items },
+                             { &c.cap_patches, &c.cap_items }, "batch tables")))
+        return r;
     const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
     std::vector<gd::PatchDesc> desc(npatch);
     std::vector<gd::WorkItem> items;
@@ -241,12 +350,12 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
                 }
     }
     if (items.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many work items");
-    int r;
     if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
     if ((r = ensure_capacity(ctx, &c.d_items, &c.cap_items, items.size()))) return r;
-    // The tables are written before any kernel that reads them: a synchronous
-    // copy keeps the host vectors' lifetime out of the stream.
-    hipError_t e = hipStreamSynchronize(s);
+    // The tables are written before any kernel that reads them (the device
+    // waited above): a synchronous copy keeps the host vectors' lifetime out
+    // of the stream.
+    hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_items, items.data(), items.size() * sizeof(gd::WorkItem), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "upload of batch tables");
@@ -262,7 +371,14 @@ int build_cfl_tables(gd_ctx *ctx, bool periodic, int npatch, const gd_patch *pat
 {
     BatchCache &c = cache ? *cache : ctx->cfl;
     int tag = periodic ? 1 : 0;
-    if (c.dtype == tag && same_patches(c, npatch, patches)) return GD_OK;
+    if (c.dtype == tag && same_patches(c, npatch, patches)) {
+        if (capturing(s)) c.captured = true;
+        return GD_OK;
+    }
+    int r;
+    if ((r = prepare_rebuild(ctx, s, c.captured, { (void **)&c.d_patches, (void **)&c.d_cfl_items },
+                             { &c.cap_patches, &c.cap_cfl }, "CFL tables")))
+        return r;
     std::vector<gd::PatchDesc> desc(npatch);
     std::vector<gd::CflItem> items;
     for (int i = 0; i < npatch; ++i) {
@@ -275,10 +391,9 @@ int build_cfl_tables(gd_ctx *ctx, bool periodic, int npatch, const gd_patch *pat
                 items.push_back(gd::CflItem{ i, k, j0, std::min(rows, p.ny - j0) });
     }
     if (items.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many cfl items");
-    int r;
     if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
     if ((r = ensure_capacity(ctx, &c.d_cfl_items, &c.cap_cfl, items.size()))) return r;
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_cfl_items, items.data(), items.size() * sizeof(gd::CflItem), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "upload of cfl tables");
@@ -313,10 +428,11 @@ int gd_create(gd_ctx **out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
     if (ctx->num_cus < 1) ctx->num_cus = 256;
-    e = hipMalloc((void **)&ctx->d_u64, 8 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_u32, 4 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, 8 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemset(ctx->d_u32, 0, 4 * sizeof(unsigned));
+    const size_t n64 = SLOT_U64 * (NSLOT + 1), n32 = SLOT_U32 * NSLOT;
+    e = hipMalloc((void **)&ctx->d_u64, n64 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_u32, n32 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(ctx->d_u64, 0, n64 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(ctx->d_u32, 0, n32 * sizeof(unsigned));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         gd_destroy(ctx);
@@ -336,9 +452,9 @@ int gd_destroy(gd_ctx *ctx)
         if (c->d_items) (void)hipFree(c->d_items);
         if (c->d_cfl_items) (void)hipFree(c->d_cfl_items);
     }
-    if (ctx->d_adj) (void)hipFree(ctx->d_adj);
-    if (ctx->d_mhd) (void)hipFree(ctx->d_mhd);
-    if (ctx->d_ppm) (void)hipFree(ctx->d_ppm);
+    for (Scratch *sc : { &ctx->adj, &ctx->mhd, &ctx->ppm_s })
+        if (sc->p) (void)hipFree(sc->p);
+    for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->ppm.d_patches) (void)hipFree(ctx->ppm.d_patches);
     if (ctx->ppm.d_pitems) (void)hipFree(ctx->ppm.d_pitems);
     if (ctx->ppm.d_uitems) (void)hipFree(ctx->ppm.d_uitems);
@@ -386,19 +502,9 @@ int gd_reset_stats(gd_ctx *ctx)
 
 namespace {
 
-int ensure_ppm_scratch(gd_ctx *ctx, size_t need)
+int ensure_ppm_scratch(gd_ctx *ctx, size_t need, hipStream_t s)
 {
-    if (need <= ctx->ppm_bytes && ctx->d_ppm) return GD_OK;
-    // grow the scratch; work already queued may still use the old one
-    hipError_t he = hipDeviceSynchronize();
-    if (he != hipSuccess) return hip_fail(ctx, he, "PPM scratch");
-    if (ctx->d_ppm) (void)hipFree(ctx->d_ppm);
-    ctx->d_ppm = nullptr;
-    ctx->ppm_bytes = 0;
-    if (hipMalloc(&ctx->d_ppm, need) != hipSuccess)
-        return fail(ctx, GD_E_NOMEM, "PPM scratch of %zu bytes", need);
-    ctx->ppm_bytes = need;
-    return GD_OK;
+    return ensure_scratch(ctx, ctx->ppm_s, need, s, "PPM");
 }
 
 // Work tables of a PPM batch: 256-cell pieces of each patch's scratch box
@@ -407,8 +513,17 @@ int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream
 {
     PpmCache &c = ctx->ppm;
     if ((int)c.host.size() == npatch &&
-        std::memcmp(c.host.data(), patches, npatch * sizeof(gd_patch)) == 0)
+        std::memcmp(c.host.data(), patches, npatch * sizeof(gd_patch)) == 0) {
+        if (capturing(s)) c.captured = true;
         return GD_OK;
+    }
+    int r;
+    if ((r = prepare_rebuild(ctx, s, c.captured,
+                             { (void **)&c.d_patches, (void **)&c.d_pitems, (void **)&c.d_uitems,
+                               (void **)&c.d_soff },
+                             { &c.cap_patches, &c.cap_pitems, &c.cap_uitems, &c.cap_soff },
+                             "PPM tables")))
+        return r;
     std::vector<gd::PatchDesc> desc(npatch);
     std::vector<gd::PpmTile> pit;
     std::vector<gd::PpmItem> uit;
@@ -430,12 +545,11 @@ int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream
         for (int64_t a = 0; a < cells; a += 256) uit.push_back(gd::PpmItem{ i, (int32_t)a });
     }
     if (pit.size() > 0x7fffffff || uit.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many PPM items");
-    int r;
     if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
     if ((r = ensure_capacity(ctx, &c.d_pitems, &c.cap_pitems, pit.size()))) return r;
     if ((r = ensure_capacity(ctx, &c.d_uitems, &c.cap_uitems, uit.size()))) return r;
     if ((r = ensure_capacity(ctx, &c.d_soff, &c.cap_soff, soff.size()))) return r;
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_pitems, pit.data(), pit.size() * sizeof(gd::PpmTile), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c.d_uitems, uit.data(), uit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
@@ -478,31 +592,32 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     P.in_off = 0; P.out_off = 0; P.flux_off = bflux ? 0 : -1;
     P.dx = dx; P.dt = dt;
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Slot slot = slot_for(ctx, s);
     if (is_ppm(opts)) {
-        hipStream_t s = (hipStream_t)hip_stream;
-        if ((r = ensure_ppm_scratch(ctx, (size_t)gd::ppm_box_cells(P) * 30 * es))) return r;
+        if ((r = ensure_ppm_scratch(ctx, (size_t)gd::ppm_box_cells(P) * 30 * es, s))) return r;
         int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, P, nullptr, nullptr, 0,
-                               nullptr, 0, nullptr, u_in, u_out, bflux, ctx->d_ppm, dt_dev, sc,
+                               nullptr, 0, nullptr, u_in, u_out, bflux, ctx->ppm_s.p, dt_dev, sc,
                                ctx->d_u64, s);
         if (e) return hip_fail(ctx, e, "PPM step launch");
         if (dt_next) {
             // the CFL step of the new state, reduced over u_out
             gd::PatchDesc Po = P;
             Po.periodic = 1; Po.ng = 0;
-            e = gd::launch_cfl_single(opts->dtype, Po, u_out, sc, cfl, dt_next, ctx->d_u64 + 2,
-                                      ctx->d_u32 + 3, s);
+            e = gd::launch_cfl_single(opts->dtype, Po, u_out, sc, cfl, dt_next, slot.u64 + 2,
+                                      slot.u32 + 3, s);
             if (e) return hip_fail(ctx, e, "PPM step CFL launch");
         }
         return GD_OK;
     }
-    gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
+    gd::CflOut co{ cfl, dt_next, slot.u64 + 2, slot.u32 + 3 };
     // the workgroups the chip holds at once: fewer leave CUs idle
     const int shape = ctx->shape_single[opts->dtype];
     const int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, shape,
                                                ctx->device);
     int e = gd::launch_step(opts->dtype, opts->limiter, opts->riemann, shape, P, u_in, u_out,
                             bflux, dt_dev, sc, ctx->d_u64, ctx->zlen_single[opts->dtype],
-                            per_cu * ctx->num_cus, co, (hipStream_t)hip_stream);
+                            per_cu * ctx->num_cus, co, s);
     if (e) return hip_fail(ctx, e, "godunov_step launch");
     return GD_OK;
 }
@@ -544,15 +659,16 @@ int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_pat
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
+    const Slot slot = slot_for(ctx, s);
     if (is_ppm(opts)) {
         gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
         if ((r = build_ppm_tables(ctx, npatch, patches, s))) return r;
         const PpmCache &c = ctx->ppm;
-        if ((r = ensure_ppm_scratch(ctx, (size_t)c.scratch_elems * es))) return r;
+        if ((r = ensure_ppm_scratch(ctx, (size_t)c.scratch_elems * es, s))) return r;
         gd::PatchDesc none{};
         int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, none, c.d_patches, c.d_pitems,
                                c.npitems, c.d_uitems, c.nuitems, c.d_soff, u_in_base, u_out_base,
-                               bflux_base, ctx->d_ppm, dt_dev, sc, ctx->d_u64, s);
+                               bflux_base, ctx->ppm_s.p, dt_dev, sc, ctx->d_u64, s);
         if (e) return hip_fail(ctx, e, "PPM batched step launch");
         if (dt_next) {
             // the batch's CFL step, reduced over the outputs (interior layout)
@@ -562,7 +678,7 @@ int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_pat
             const BatchCache &cc = ctx->ppm_cfl;
             int grid = std::min(cc.ncfl, 8 * ctx->num_cus);
             e = gd::launch_cfl(opts->dtype, cc.d_patches, cc.d_cfl_items, cc.ncfl, u_out_base, sc, cfl,
-                               dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3, std::max(grid, 1), s);
+                               dt_next, slot.u64 + 2, slot.u32 + 3, std::max(grid, 1), s);
             if (e) return hip_fail(ctx, e, "PPM batched CFL launch");
         }
         return GD_OK;
@@ -574,10 +690,10 @@ int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_pat
     int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, c.shape, ctx->device);
     int grid = std::min(c.nitems, per_cu * ctx->num_cus);
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
-    gd::CflOut co{ cfl, dt_next, ctx->d_u64 + 2, ctx->d_u32 + 3 };
+    gd::CflOut co{ cfl, dt_next, slot.u64 + 2, slot.u32 + 3 };
     int e = gd::launch_step_batched(opts->dtype, opts->limiter, opts->riemann, c.shape, c.d_patches,
                                     c.d_items, c.nitems, u_in_base, u_out_base, bflux_base, dt_dev,
-                                    sc, ctx->d_u64, ctx->d_u32, std::max(grid, 1), co, s);
+                                    sc, ctx->d_u64, slot.u32, std::max(grid, 1), co, s);
     if (e) return hip_fail(ctx, e, "godunov_step_batched launch");
     return GD_OK;
 }
@@ -636,18 +752,19 @@ int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
+    const Slot slot = slot_for(ctx, s);
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
     int e;
     if (npatch == 1) {
         gd::PatchDesc P = to_desc(patches[0], periodic);
-        e = gd::launch_cfl_single(opts->dtype, P, u_base, sc, cfl, dt_dev, ctx->d_u64 + 1,
-                                  ctx->d_u32 + 2, s);
+        e = gd::launch_cfl_single(opts->dtype, P, u_base, sc, cfl, dt_dev, slot.u64 + 1,
+                                  slot.u32 + 2, s);
     } else {
         if ((r = build_cfl_tables(ctx, periodic, npatch, patches, s))) return r;
         const BatchCache &c = ctx->cfl;
         int grid = std::min(c.ncfl, 8 * ctx->num_cus);
         e = gd::launch_cfl(opts->dtype, c.d_patches, c.d_cfl_items, c.ncfl, u_base, sc, cfl, dt_dev,
-                           ctx->d_u64 + 1, ctx->d_u32 + 2, std::max(grid, 1), s);
+                           slot.u64 + 1, slot.u32 + 2, std::max(grid, 1), s);
     }
     if (e) return hip_fail(ctx, e, "cfl_dt launch");
     return GD_OK;
@@ -681,21 +798,11 @@ int godunov_step_adjoint(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int n
     if ((r = set_device(ctx))) return r;
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t need = gd::adjoint_scratch_bytes(P);
-    if (need > ctx->adj_bytes) {
-        // grow the scratch; work already queued may still use the old one
-        hipError_t he = hipDeviceSynchronize();
-        if (he != hipSuccess) return hip_fail(ctx, he, "adjoint scratch");
-        if (ctx->d_adj) (void)hipFree(ctx->d_adj);
-        ctx->d_adj = nullptr;
-        ctx->adj_bytes = 0;
-        if (hipMalloc((void **)&ctx->d_adj, need) != hipSuccess)
-            return fail(ctx, GD_E_NOMEM, "adjoint scratch of %zu bytes", need);
-        ctx->adj_bytes = need;
-    }
+    if ((r = ensure_scratch(ctx, ctx->adj, need, s, "adjoint"))) return r;
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
     int e = gd::launch_adjoint(opts->limiter, opts->riemann, P, (const double *)u_in,
                                (const double *)lam_out, (const double *)lam_bflux, (double *)lam_in,
-                               sc, dt, ctx->d_adj, s);
+                               sc, dt, (double *)ctx->adj.p, s);
     if (e) return hip_fail(ctx, e, "godunov_step_adjoint launch");
     return GD_OK;
 }
@@ -744,6 +851,8 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
     int r;
     if ((r = check_opts(ctx, opts))) return r;
     if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
+    if (capturing((hipStream_t)hip_stream))
+        return fail(ctx, GD_E_UNSUPPORTED, "the autotuner waits on the host and cannot be captured");
     const int dt_i = opts->dtype;
     const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
                             gd::TILE_24x8 };
@@ -787,6 +896,8 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     int r;
     if ((r = check_opts(ctx, opts))) return r;
     if ((r = reject_ppm(ctx, opts, "the autotuner"))) return r;
+    if (capturing((hipStream_t)hip_stream))
+        return fail(ctx, GD_E_UNSUPPORTED, "the autotuner waits on the host and cannot be captured");
     const int dt_i = opts->dtype;
     const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
                             gd::TILE_24x8 };
@@ -890,22 +1001,13 @@ int step_mhd_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, cons
     if (overlap(u_in, bytes, u_out, bytes)) return fail(ctx, GD_E_ARG, "u_out overlaps u_in");
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
+    hipStream_t s = (hipStream_t)hip_stream;
     const size_t need = gd::mhd_scratch_bytes(opts->dtype, nx, ny, nz);
-    if (need > ctx->mhd_bytes) {
-        // grow the scratch; work already queued may still use the old one
-        hipError_t he = hipDeviceSynchronize();
-        if (he != hipSuccess) return hip_fail(ctx, he, "MHD scratch");
-        if (ctx->d_mhd) (void)hipFree(ctx->d_mhd);
-        ctx->d_mhd = nullptr;
-        ctx->mhd_bytes = 0;
-        if (hipMalloc(&ctx->d_mhd, need) != hipSuccess)
-            return fail(ctx, GD_E_NOMEM, "MHD scratch of %zu bytes", need);
-        ctx->mhd_bytes = need;
-    }
+    if ((r = ensure_scratch(ctx, ctx->mhd, need, s, "MHD"))) return r;
     gd::MhdScalars sc{ gamma, opts->rho_floor, opts->p_floor, dx, dt, ch, alpha };
     int e = gd::launch_mhd_step(opts->dtype, opts->limiter, nx, ny, nz, u_in, u_out, sc, dt_dev,
-                                ch_dev, ctx->d_mhd, cfl, dt_next, ch_next, ctx->d_u64 + 6,
-                                (hipStream_t)hip_stream);
+                                ch_dev, ctx->mhd.p, cfl, dt_next, ch_next,
+                                slot_for(ctx, s).u64 + 6, s);
     if (e) return hip_fail(ctx, e, "godunov_step_mhd launch");
     return GD_OK;
 }
@@ -946,7 +1048,8 @@ int cfl_dt_mhd(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, const v
     if ((r = set_device(ctx))) return r;
     gd::MhdScalars sc{ gamma, opts->rho_floor, opts->p_floor, dx, 0.0, 0.0, 0.0 };
     int e = gd::launch_mhd_speeds(opts->dtype, nx, ny, nz, u, sc, cfl, dt_dev, ch_dev,
-                                  ctx->d_u64 + 4, (hipStream_t)hip_stream);
+                                  slot_for(ctx, (hipStream_t)hip_stream).u64 + 4,
+                                  (hipStream_t)hip_stream);
     if (e) return hip_fail(ctx, e, "cfl_dt_mhd launch");
     return GD_OK;
 }
@@ -1502,6 +1605,8 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
         return fail(ctx, GD_E_ARG, "bflux_host range overlaps u_in_host or u_out_host");
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if ((r = set_device(ctx))) return r;
+    if (capturing((hipStream_t)hip_stream))
+        return fail(ctx, GD_E_UNSUPPORTED, "a streamed batch cannot be captured into a graph");
     if (!ctx->stream) ctx->stream = new gd_stream_state();
     gd_stream_state &st = *ctx->stream;
     hipStream_t caller = (hipStream_t)hip_stream;
@@ -1520,7 +1625,8 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
     const int per_cu = gd::max_resident_blocks(opts->dtype, opts->limiter, opts->riemann, st.shape,
                                                ctx->device);
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
-    gd::CflOut co{ 0.0, nullptr, ctx->d_u64 + 2, ctx->d_u32 + 3 };
+    const Slot cslot = slot_for(ctx, st.s_comp);
+    gd::CflOut co{ 0.0, nullptr, cslot.u64 + 2, cslot.u32 + 3 };
     const char *hin = (const char *)u_in_host;
     char *hout = (char *)u_out_host, *hfl = (char *)bflux_host;
     for (size_t c = 0; c < st.chunks.size() && e == hipSuccess; ++c) {
@@ -1543,7 +1649,7 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
             int ke = gd::launch_step_batched(opts->dtype, opts->limiter, opts->riemann, st.shape,
                                              st.d_patches, st.d_items + ch.item0, ch.nitems, sin, sout,
                                              ch.fl_elems ? sfl : nullptr, dt_dev, sc, ctx->d_u64,
-                                             ctx->d_u32, grid, co, st.s_comp);
+                                             cslot.u32, grid, co, st.s_comp);
             if (ke) e = (hipError_t)ke;
         }
         if (e == hipSuccess) e = hipEventRecord(st.ev_comp[b], st.s_comp);

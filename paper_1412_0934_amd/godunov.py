@@ -208,8 +208,46 @@ def _check_tensor(t, name, dtype=None):
         raise TypeError(f"{name} must have dtype {dtype}")
 
 
+def _check_scalar(t, name):
+    """A device scalar argument: a float64 CUDA tensor with at least one element."""
+    _check_tensor(t, name, torch.float64)
+    if t.numel() < 1:
+        raise ValueError(f"{name} must hold at least one element")
+
+
+def _check_size(t, name, need, shape=None):
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.numel() < need:
+        raise ValueError(f"{name} holds {t.numel()} values, {need} are needed")
+
+
 def bflux_size(nx, ny, nz) -> int:
     return 10 * (nz * ny + nz * nx + ny * nx)
+
+
+def batch_extents(table) -> tuple:
+    """Elements each buffer of a batched call must hold for the offsets in
+    `table` (gd_patch records): (u_in, out, bflux); the library cannot see
+    the buffers' sizes, so the binding checks them before any launch."""
+    table = np.asarray(table, dtype=PATCH_DTYPE)
+    if len(table) == 0:
+        return 0, 0, 0
+    d = np.stack([table["nx"], table["ny"], table["nz"]], axis=1).astype(np.int64)
+    g = 2 * table["ng"].astype(np.int64)[:, None]
+    need_in = int((table["u_in_off"] + 5 * np.prod(d + g, axis=1)).max())
+    need_out = int((table["u_out_off"] + 5 * np.prod(d, axis=1)).max())
+    fl = 10 * (d[:, 2] * d[:, 1] + d[:, 2] * d[:, 0] + d[:, 1] * d[:, 0])
+    has = table["flux_off"] >= 0
+    need_fl = int((table["flux_off"][has] + fl[has]).max()) if has.any() else 0
+    return need_in, need_out, need_fl
+
+
+def _check_batch(table, u_in, out=None, bflux=None):
+    need_in, need_out, need_fl = batch_extents(table)
+    for name, t, need in (("u_in", u_in, need_in), ("out", out, need_out), ("bflux", bflux, need_fl)):
+        if t is not None:
+            _check_size(t, name, need)
 
 
 def interior_shape(u, ng, periodic):
@@ -232,18 +270,22 @@ def step(u, gamma, dx, dt=None, *, dt_dev=None, ng=2, periodic=False, limiter="m
     if out is None:
         out = torch.empty((5, nz, ny, nx), dtype=u.dtype, device=u.device)
     _check_tensor(out, "out", u.dtype)
+    _check_size(out, "out", 0, (5, nz, ny, nx))
     if want_bflux and bflux is None:
         bflux = torch.empty(bflux_size(nx, ny, nz), dtype=u.dtype, device=u.device)
     if not want_bflux:
         bflux = None
+    if bflux is not None:
+        _check_tensor(bflux, "bflux", u.dtype)
+        _check_size(bflux, "bflux", bflux_size(nx, ny, nz))
     if dt_dev is not None:
-        _check_tensor(dt_dev, "dt_dev", torch.float64)
+        _check_scalar(dt_dev, "dt_dev")
     if dt is None and dt_dev is None:
         raise ValueError("give dt or dt_dev")
     ctx = context(u.device.index)
     o = _opts(u.dtype, periodic, limiter, riemann, rho_floor, p_floor)
     if dt_next is not None:
-        _check_tensor(dt_next, "dt_next", torch.float64)
+        _check_scalar(dt_next, "dt_next")
         ctx.check(ctx.lib.godunov_step_cfl(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u),
                                            _ptr(out), _ptr(bflux), float(gamma), float(dx),
                                            float(dt if dt is not None else 0.0), _ptr(dt_dev),
@@ -264,7 +306,7 @@ def cfl_dt(u, gamma, dx, cfl=0.5, *, ng=2, periodic=False, out=None, rho_floor=R
     nx, ny, nz = interior_shape(u, ng, periodic)
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=u.device)
-    _check_tensor(out, "out", torch.float64)
+    _check_scalar(out, "out")
     ctx = context(u.device.index)
     o = _opts(u.dtype, periodic, "minmod", "hllc", rho_floor, p_floor)
     desc = np.zeros(1, dtype=PATCH_DTYPE)
@@ -298,12 +340,13 @@ def step_batched(u_in, table, gamma, *, out, bflux=None, dt_dev=None, limiter="m
     if bflux is not None:
         _check_tensor(bflux, "bflux", u_in.dtype)
     if dt_dev is not None:
-        _check_tensor(dt_dev, "dt_dev", torch.float64)
+        _check_scalar(dt_dev, "dt_dev")
     table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    _check_batch(table, u_in, out, bflux)
     ctx = context(u_in.device.index)
     o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
     if dt_next is not None:
-        _check_tensor(dt_next, "dt_next", torch.float64)
+        _check_scalar(dt_next, "dt_next")
         ctx.check(ctx.lib.godunov_step_batched_cfl(
             ctx.handle, ctypes.byref(o), len(table), table.ctypes.data, _ptr(u_in), _ptr(out),
             _ptr(bflux), _ptr(dt_dev), float(gamma), float(0.5 if cfl is None else cfl),
@@ -332,19 +375,9 @@ def step_batched_streamed(u_in, table, gamma, *, out, bflux=None, chunk_bytes=25
         if t.dtype != u_in.dtype:
             raise TypeError(f"{name} must have dtype {u_in.dtype}")
     if dt_dev is not None:
-        _check_tensor(dt_dev, "dt_dev", torch.float64)
+        _check_scalar(dt_dev, "dt_dev")
     table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
-    # the library cannot see the host buffers' sizes: check them here
-    d = np.stack([table["nx"], table["ny"], table["nz"]], axis=1).astype(np.int64)
-    g = 2 * table["ng"].astype(np.int64)[:, None]
-    need_in = int((table["u_in_off"] + 5 * np.prod(d + g, axis=1)).max()) if len(d) else 0
-    need_out = int((table["u_out_off"] + 5 * np.prod(d, axis=1)).max()) if len(d) else 0
-    fl = 10 * (d[:, 2] * d[:, 1] + d[:, 2] * d[:, 0] + d[:, 1] * d[:, 0])
-    has = table["flux_off"] >= 0
-    need_fl = int((table["flux_off"][has] + fl[has]).max()) if has.any() else 0
-    for name, t, need in (("u_in", u_in, need_in), ("out", out, need_out), ("bflux", bflux, need_fl)):
-        if t is not None and t.numel() < need:
-            raise ValueError(f"{name} holds {t.numel()} values, the patches need {need}")
+    _check_batch(table, u_in, out, bflux)
     ctx = context(device)
     o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
     ctx.check(ctx.lib.godunov_step_batched_streamed(
@@ -358,7 +391,9 @@ def cfl_dt_batched(u_in, table, gamma, cfl=0.5, *, out=None, rho_floor=RHO_FLOOR
     _check_tensor(u_in, "u_in")
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=u_in.device)
+    _check_scalar(out, "out")
     table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    _check_batch(table, u_in)
     ctx = context(u_in.device.index)
     o = _opts(u_in.dtype, False, "minmod", "hllc", rho_floor, p_floor)
     ctx.check(ctx.lib.cfl_dt(ctx.handle, ctypes.byref(o), len(table), table.ctypes.data,
@@ -377,8 +412,11 @@ def step_adjoint(u, lam_out, gamma, dx, dt, *, lam_bflux=None, ng=2, periodic=Fa
         raise ValueError("lam_out has the wrong shape")
     if lam_bflux is not None:
         _check_tensor(lam_bflux, "lam_bflux", torch.float64)
+        _check_size(lam_bflux, "lam_bflux", bflux_size(nx, ny, nz))
     if out is None:
         out = torch.empty_like(u)
+    _check_tensor(out, "out", torch.float64)
+    _check_size(out, "out", 0, u.shape)
     ctx = context(u.device.index)
     o = _opts(torch.float64, periodic, limiter, riemann, rho_floor, p_floor)
     ctx.check(ctx.lib.godunov_step_adjoint(ctx.handle, ctypes.byref(o), nx, ny, nz, ng, _ptr(u),
@@ -398,6 +436,8 @@ def autotune_step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", r
     nx, ny, nz = interior_shape(u, ng, periodic)
     if out is None:
         out = torch.empty((5, nz, ny, nx), dtype=u.dtype, device=u.device)
+    _check_tensor(out, "out", u.dtype)
+    _check_size(out, "out", 0, (5, nz, ny, nx))
     ctx = context(u.device.index)
     o = _opts(u.dtype, periodic, limiter, riemann, rho_floor, p_floor)
     choice = ctypes.c_int(-1)
@@ -410,7 +450,11 @@ def autotune_step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", r
 def autotune_batched(u_in, table, gamma, *, out, bflux=None, limiter="minmod", riemann="hllc",
                      rho_floor=RHO_FLOOR, p_floor=P_FLOOR, stream=None) -> int:
     _check_tensor(u_in, "u_in")
+    _check_tensor(out, "out", u_in.dtype)
+    if bflux is not None:
+        _check_tensor(bflux, "bflux", u_in.dtype)
     table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    _check_batch(table, u_in, out, bflux)
     ctx = context(u_in.device.index)
     o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
     choice = ctypes.c_int(-1)
@@ -498,13 +542,14 @@ def step_mhd(u, gamma, dx, dt=None, ch=None, *, dt_dev=None, ch_dev=None, alpha=
     if out is None:
         out = torch.empty_like(u)
     _check_tensor(out, "out", u.dtype)
+    _check_size(out, "out", 0, u.shape)
     if dt is None and dt_dev is None:
         raise ValueError("give dt or dt_dev")
     if ch is None and ch_dev is None:
         raise ValueError("give ch or ch_dev")
     for t, name in ((dt_dev, "dt_dev"), (ch_dev, "ch_dev")):
         if t is not None:
-            _check_tensor(t, name, torch.float64)
+            _check_scalar(t, name)
     ctx = context(u.device.index)
     o = _opts(u.dtype, True, limiter, "hllc", rho_floor, p_floor)
     if dt_next is None and ch_next is None:
@@ -515,7 +560,7 @@ def step_mhd(u, gamma, dx, dt=None, ch=None, *, dt_dev=None, ch_dev=None, alpha=
         return out
     for t, name in ((dt_next, "dt_next"), (ch_next, "ch_next")):
         if t is not None:
-            _check_tensor(t, name, torch.float64)
+            _check_scalar(t, name)
     if cfl is None:
         raise ValueError("dt_next / ch_next need cfl")
     ctx.check(ctx.lib.godunov_step_mhd_cfl(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u),
@@ -536,6 +581,8 @@ def cfl_dt_mhd(u, gamma, dx, cfl=0.4, *, out_dt=None, out_ch=None, rho_floor=RHO
         out_dt = torch.empty(1, dtype=torch.float64, device=u.device)
     if out_ch is None:
         out_ch = torch.empty(1, dtype=torch.float64, device=u.device)
+    _check_scalar(out_dt, "out_dt")
+    _check_scalar(out_ch, "out_ch")
     ctx = context(u.device.index)
     o = _opts(u.dtype, True, "minmod", "hllc", rho_floor, p_floor)
     ctx.check(ctx.lib.cfl_dt_mhd(ctx.handle, ctypes.byref(o), nx, ny, nz, _ptr(u), float(gamma),
@@ -615,7 +662,7 @@ class AmrPlan:
         self._check([("coarse_old", coarse_old), ("coarse_new", coarse_new)], fine_out=fine_out,
                     fine_flux=fine_flux)
         if dt_dev is not None:
-            _check_tensor(dt_dev, "dt_dev", torch.float64)
+            _check_scalar(dt_dev, "dt_dev")
         o = _opts(coarse_old.dtype, True, limiter, riemann, rho_floor, p_floor)
         self.ctx.check(self.ctx.lib.gd_amr_reflux(
             self.ctx.handle, self.handle, ctypes.byref(o), _ptr(coarse_old), _ptr(coarse_new),
@@ -635,7 +682,7 @@ class AmrPlan:
             if t.dtype != coarse_in.dtype:
                 raise TypeError(f"{name} must have dtype {coarse_in.dtype}")
         if dt_dev is not None:
-            _check_tensor(dt_dev, "dt_dev", torch.float64)
+            _check_scalar(dt_dev, "dt_dev")
         elif dt is None:
             raise ValueError("give dt or dt_dev")
         o = _opts(coarse_in.dtype, True, limiter, riemann, rho_floor, p_floor)

@@ -272,3 +272,29 @@ def test_step_without_a_gpu_raises():
         pytest.skip("a GPU is present")
     assert r.returncode == 0, r.stderr
     assert "must be a CUDA tensor" in r.stdout and "no CPU path" in r.stdout
+
+
+def test_batch_extents_cover_the_packed_layout():
+    """The binding's buffer-size check for batched calls: the extents it
+    derives from the descriptors equal the packed buffers' sizes, and any
+    shorter buffer is refused."""
+    import numpy as np
+    import torch
+    from paper_1412_0934_amd import godunov, inputs
+    batch = inputs.batch_layout([(3, 4, 5), (8, 8, 8), (1, 1, 1), (2, 7, 3)], 2, 0.1, order_seed=3)
+    t = godunov.patch_table(batch.dims, 2, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                            batch.dx)
+    assert godunov.batch_extents(t) == (batch.u_in.size, batch.u_out_size, batch.flux_size)
+    full = [torch.empty(n) for n in (batch.u_in.size, batch.u_out_size, batch.flux_size)]
+    godunov._check_batch(t, *full)
+    for i in range(3):
+        args = list(full)
+        args[i] = args[i][:-1]
+        with pytest.raises(ValueError):
+            godunov._check_batch(t, *args)
+    t["flux_off"] = -1
+    assert godunov.batch_extents(t)[2] == 0
+    assert godunov.batch_extents(t[:0]) == (0, 0, 0)
+    with pytest.raises(ValueError):
+        godunov._check_size(torch.empty(3), "x", 0, (4,))
+    assert np.all(t["nx"] >= 1)
