@@ -39,9 +39,13 @@ RHO_FLOOR = 1e-10
 P_FLOOR = 1e-10
 
 
-def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE) -> None:
-    """Compile both oracle libraries with gcc (plain C11 + OpenMP)."""
-    common = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v2"]
+def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE,
+          extra_flags=()) -> None:
+    """Compile the oracle libraries with gcc (plain C11 + OpenMP). The default
+    build has no FMA contraction (x86-64-v2); extra_flags (e.g. "-mfma",
+    "-ffp-contract=fast") give another valid rounding of the same arithmetic."""
+    common = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v2",
+              *extra_flags]
     cmds = [
         common + ["-o", os.path.join(out_dir, "liboracle.so"),
                   os.path.join(src_dir, "godunov_oracle_adjoint.c"), "-lm"],

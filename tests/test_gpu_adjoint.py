@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import rel_norm_err, say
+from helpers import say
 from paper_1412_0934_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -207,7 +207,13 @@ def test_rollout_gradient_matches_central_differences_128(gd, lim, rs, direction
     errs = np.array(errs)
     say("FD relative errors (%s): median %.2e  90%% %.2e  max %.2e"
         % (directions, np.median(errs), np.percentile(errs, 90), errs.max()))
+    say("FD relative error per direction (%s, %s, %s): %s"
+        % (lim, rs, directions, " ".join(f"{e:.2e}" for e in errs)))
+    # bounds about three times the errors recorded on one MI355X (these
+    # directions and kernels are deterministic): unlimited HLL median 3.3e-8,
+    # max 6.4e-6; minmod + HLLC median 3.2e-7, 90th percentile 1.3e-5,
+    # max 1.24e-4
     if lim == "none":
-        assert np.median(errs) <= 1e-6 and errs.max() <= 1e-4, errs
+        assert np.median(errs) <= 1e-7 and errs.max() <= 2e-5, errs
     else:
-        assert np.median(errs) <= 1e-4 and np.sum(errs <= 1e-3) >= 56, errs
+        assert np.median(errs) <= 1e-6 and errs.max() <= 4e-4, errs

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import rel_norm_err, say
+from helpers import bflux_err, parity_err, say
 from paper_1412_0934_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -63,8 +63,8 @@ def test_batch_with_maximum_extents(gd):
     out, flux = run_batched(gd, batch, dts, torch.float64)
     for p, u in enumerate(states):
         ref, rflux, _ = oracle.step(u, G, 1 / 64, dts[p])
-        assert rel_norm_err(batch.patch_out(out, p), ref) <= 1e-12, p
-        assert rel_norm_err(batch.patch_flux(flux, p), rflux) <= 1e-12, p
+        assert parity_err(batch.patch_out(out, p), ref) <= 1e-12, p
+        assert bflux_err(batch.patch_flux(flux, p), rflux, *batch.dims[p]) <= 1e-12, p
 
 
 @pytest.mark.parametrize("lim,rs", [("minmod", "hllc"), ("mc", "hll"), ("none", "hllc")])
@@ -79,8 +79,8 @@ def test_small_batch_matches_oracle_and_single_patch(gd, lim, rs):
     for p in range(batch.npatch):
         u = batch.patch_in(p)
         ref, rflux, _ = oracle.step(u, G, batch.dx[p], dts[p], limiter=lim, riemann=rs)
-        assert rel_norm_err(batch.patch_out(out, p), ref) <= 1e-12, p
-        assert rel_norm_err(batch.patch_flux(flux, p), rflux) <= 1e-12, p
+        assert parity_err(batch.patch_out(out, p), ref) <= 1e-12, p
+        assert bflux_err(batch.patch_flux(flux, p), rflux, *batch.dims[p]) <= 1e-12, p
         single, sflux = gd.step(torch.from_numpy(u).cuda(), G, batch.dx[p], dts[p], limiter=lim,
                                 riemann=rs)
         assert np.array_equal(batch.patch_out(out, p), host(single)), p
@@ -96,8 +96,8 @@ def test_small_batch_fp32(gd):
     out, flux = run_batched(gd, batch, dts, torch.float32)
     for p in range(batch.npatch):
         ref, rflux, _ = oracle.step(batch.patch_in(p), G, batch.dx[p], dts[p])
-        assert rel_norm_err(batch.patch_out(out, p), ref) <= 1e-5, p
-        assert rel_norm_err(batch.patch_flux(flux, p), rflux) <= 1e-5, p
+        assert parity_err(batch.patch_out(out, p), ref) <= 1e-5, p
+        assert bflux_err(batch.patch_flux(flux, p), rflux, *batch.dims[p]) <= 1e-5, p
 
 
 def test_batched_cfl_and_device_dt(gd):
@@ -116,7 +116,7 @@ def test_batched_cfl_and_device_dt(gd):
     out, _ = run_batched(gd, batch, np.zeros(batch.npatch), torch.float64, dt_dev=dt_dev)
     for p in range(0, batch.npatch, 5):
         ref, _, _ = oracle.step(batch.patch_in(p), G, batch.dx[p], got)
-        assert rel_norm_err(batch.patch_out(out, p), ref) <= 1e-12, p
+        assert parity_err(batch.patch_out(out, p), ref) <= 1e-12, p
 
 
 def test_repeated_calls_reuse_tables_and_agree(gd):
@@ -132,46 +132,96 @@ def test_repeated_calls_reuse_tables_and_agree(gd):
 
 @pytest.fixture(scope="module")
 def amr():
-    return inputs.amr_batch(4096, seed=5)
+    """The 4096-patch batch, its CFL dt, and the oracle's step of every patch
+    (outputs and boundary fluxes in the batch's flat layouts)."""
+    batch = inputs.amr_batch(4096, seed=5)
+    dt = 0.5 * min(batch.dx[p] / oracle.max_signal(batch.patch_in(p), G)
+                   for p in range(batch.npatch))
+    say("amr batch: oracle step of every patch")
+    ref_out = np.empty(batch.u_out_size)
+    ref_flux = np.empty(batch.flux_size)
+    for p in range(batch.npatch):
+        o, f, _ = oracle.step(batch.patch_in(p), G, batch.dx[p], dt)
+        batch.patch_out(ref_out, p)[...] = o
+        batch.patch_flux(ref_flux, p)[...] = f
+    return batch, dt, ref_out, ref_flux
 
 
-@pytest.mark.parametrize("dtype_name,shape,policy", [("f64", "16x16", 1), ("f64", "24x8", 2),
-                                                     ("f32", "16x16", 1), ("f32", "24x8", 2)])
-def test_full_amr_batch(gd, amr, dtype_name, shape, policy):
-    """4096 patches 8^3..32^3 in one persistent launch, in the default
-    configuration and in the one the autotuner picks for this batch (24x8
-    tiles, whole-patch z-ranges): oracle parity on a seeded sample of
-    patches, and the boundary-flux telescoping identity on every patch."""
-    import torch
-    dtype = torch.float64 if dtype_name == "f64" else torch.float32
-    tol = 1e-12 if dtype_name == "f64" else 1e-5
-    rng = np.random.default_rng(77)
-    sample = rng.choice(amr.npatch, size=48, replace=False)
-    dt = 0.5 * min(amr.dx[p] / oracle.max_signal(amr.patch_in(p), G) for p in range(amr.npatch))
-    say("amr batch", dtype_name, shape, policy)
-    try:
-        gd.set_config(dtype, shape_batched=shape, zpolicy_batched=policy)
-        out, flux = run_batched(gd, amr, np.full(amr.npatch, dt), dtype)
-    finally:
-        gd.set_config(dtype)
-    assert np.all(np.isfinite(out)) and np.all(np.isfinite(flux))
-    for p in sample:
-        ref, rflux, _ = oracle.step(amr.patch_in(p), G, amr.dx[p], dt)
-        assert rel_norm_err(amr.patch_out(out, p), ref) <= tol, p
-        assert rel_norm_err(amr.patch_flux(flux, p), rflux) <= tol, p
-    if dtype_name == "f32":
-        return
-    for p in range(amr.npatch):
-        nx, ny, nz = (int(v) for v in amr.dims[p])
-        sh = oracle.split_bflux(amr.patch_flux(flux, p), nx, ny, nz)
-        before = amr.patch_in(p)[:, 2:-2, 2:-2, 2:-2]
-        after = amr.patch_out(out, p)
+def check_every_patch(batch, out, flux, ref_out, ref_flux, tol):
+    worst = 0.0
+    for p in range(batch.npatch):
+        e = max(parity_err(batch.patch_out(out, p), batch.patch_out(ref_out, p)),
+                bflux_err(batch.patch_flux(flux, p), batch.patch_flux(ref_flux, p), *batch.dims[p]))
+        assert e <= tol, (p, e)
+        worst = max(worst, e)
+    return worst
+
+
+def check_telescoping(batch, out, flux, dt):
+    for p in range(batch.npatch):
+        nx, ny, nz = (int(v) for v in batch.dims[p])
+        sh = oracle.split_bflux(batch.patch_flux(flux, p), nx, ny, nz)
+        before = batch.patch_in(p)[:, 2:-2, 2:-2, 2:-2]
+        after = batch.patch_out(out, p)
         for v in (0, 4):
             lhs = math.fsum(after[v].ravel()) - math.fsum(before[v].ravel())
             net = sum(math.fsum(sh[s][v].ravel()) * sg for s, sg in
                       (("x+", 1), ("x-", -1), ("y+", 1), ("y-", -1), ("z+", 1), ("z-", -1)))
             scale = math.fsum(np.abs(before[v]).ravel())
-            assert abs(lhs + dt / amr.dx[p] * net) <= 1e-12 * scale, (p, v)
+            assert abs(lhs + dt / batch.dx[p] * net) <= 1e-12 * scale, (p, v)
+
+
+@pytest.mark.parametrize("dtype_name,shape,policy", [
+    ("f64", "16x16", 1), ("f64", "16x8", 2), ("f64", "24x8", 2),
+    ("f32", "16x16", 1), ("f32", "24x8", 2), ("f32", "16x8", 2)])
+def test_full_amr_batch(gd, amr, dtype_name, shape, policy):
+    """4096 patches 8^3..32^3 in one persistent launch, in the default
+    configuration and in the ones the autotuner picks for this batch on one
+    MI355X (FP64: 16x8 tiles, FP32: 24x8 tiles, whole-patch z-ranges, which
+    the benchmark times), every patch against the oracle element by element,
+    and (FP64) the boundary-flux telescoping identity on every patch."""
+    import torch
+    batch, dt, ref_out, ref_flux = amr
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    tol = 1e-12 if dtype_name == "f64" else 1e-5
+    say("amr batch", dtype_name, shape, policy)
+    try:
+        gd.set_config(dtype, shape_batched=shape, zpolicy_batched=policy)
+        out, flux = run_batched(gd, batch, np.full(batch.npatch, dt), dtype)
+    finally:
+        gd.set_config(dtype)
+    assert np.all(np.isfinite(out)) and np.all(np.isfinite(flux))
+    worst = check_every_patch(batch, out, flux, ref_out, ref_flux, tol)
+    say(f"amr batch {dtype_name} {shape}/{policy}: worst patch parity {worst:.3e}")
+    if dtype_name == "f64":
+        check_telescoping(batch, out, flux, dt)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_full_amr_batch_in_the_autotuned_configuration(gd, amr, dtype_name):
+    """Whatever configuration the autotuner picks on this machine (as the
+    benchmark does before timing): every patch against the oracle."""
+    import torch
+    batch, dt, ref_out, ref_flux = amr
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    tol = 1e-12 if dtype_name == "f64" else 1e-5
+    table = gd.patch_table(batch.dims, batch.ng, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, dt)
+    u_in = torch.from_numpy(batch.u_in).to("cuda", dtype)
+    out = torch.full((batch.u_out_size,), float("nan"), dtype=dtype, device="cuda")
+    flux = torch.full((batch.flux_size,), float("nan"), dtype=dtype, device="cuda")
+    try:
+        say("amr batch autotune", dtype_name)
+        gd.autotune_batched(u_in, table, G, out=out, bflux=flux)
+        say("amr batch autotuned config", gd.get_config(dtype))
+        out.fill_(float("nan"))
+        flux.fill_(float("nan"))
+        gd.step_batched(u_in, table, G, out=out, bflux=flux)
+        o, f = host(out), host(flux)
+    finally:
+        gd.set_config(dtype)
+    worst = check_every_patch(batch, o, f, ref_out, ref_flux, tol)
+    say(f"amr batch {dtype_name} autotuned: worst patch parity {worst:.3e}")
 
 
 def test_fused_cfl_batched_step(gd):

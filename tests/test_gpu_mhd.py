@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import mhd
-from helpers import rel_norm_err, say
+from helpers import parity_err, say
 from paper_1412_0934_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -48,7 +48,7 @@ def test_random_box_matches_oracle(gd, shape, lim):
     say("mhd random box", shape, lim)
     got = host(gd.step_mhd(dev(u), G, dx, dt, ch, alpha=0.1, limiter=lim))
     assert np.all(np.isfinite(got))
-    assert rel_norm_err(got, ref, 9) <= 1e-12
+    assert parity_err(got, ref, 9) <= 1e-12
 
 
 def test_fp32_matches_oracle(gd):
@@ -59,7 +59,7 @@ def test_fp32_matches_oracle(gd):
     ref, _ = mhd.step(u, G, dx, dt, ch, alpha=0.1)
     say("mhd fp32")
     got = host(gd.step_mhd(dev(u, torch.float32), G, dx, dt, ch, alpha=0.1))
-    assert rel_norm_err(got, ref, 9) <= 1e-5
+    assert parity_err(got, ref, 9) <= 1e-5
 
 
 def test_device_cfl_and_cleaning_speed(gd):
@@ -155,7 +155,11 @@ def test_turbulent_box_128_ten_steps(gd):
             first = host(b)
         a, b = b, a
     last = host(a)
-    assert rel_norm_err(first, ref[1], 9) <= 1e-12
-    # ten steps of a turbulent field amplify rounding differences a little
-    assert rel_norm_err(last, ref[10], 9) <= 1e-10
+    e1, e10 = parity_err(first, ref[1], 9), parity_err(last, ref[10], 9)
+    say(f"mhd 128^3: parity after 1 step {e1:.3e}, after 10 steps {e10:.3e}")
+    assert e1 <= 1e-12
+    # two valid roundings of the oracle itself (with and without FMA
+    # contraction) stay within 5e-16 of each other over these ten steps, so
+    # the single-step bound holds for the rollout as well
+    assert e10 <= 1e-12
     assert _div_b(last, dx) < 0.6 * _div_b(u0, dx)
