@@ -34,4 +34,4 @@ def test_vectors_are_measured_as_vectors():
     g = f.copy()
     g[0] += 1e-9                          # mass flux of the x- sheet
     rows = bflux_vars(f, 2, 3, 4)
-    assert np.isclose(bflux_err(g, f, 2, 3, 4), 1e-9 / np.abs(rows[0]).max(), rtol=1e-6)
+    assert np.isclose(bflux_err(g, f, 2, 3, 4), 1e-9 / np.abs(rows).max(), rtol=1e-6)
