@@ -433,6 +433,40 @@ int gd_amr_step(gd_ctx *ctx, const gd_amr *plan, const gd_opts *opts, const void
                 void *coarse_out, void *fine_in_base, void *fine_out_base, void *fine_flux_base,
                 double gamma, double dt, const double *dt_dev, void *hip_stream);
 
+/* ------------------------------------------------------------ without allocation
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The batched
+ * step of godunov_step_batched with no context and no library allocation:
+ * its work queue, counters and work decomposition live in a static device
+ * array of 786,504 bytes that the library's code object carries (each GPU
+ * holds its own copy from the library's load until the process ends).
+ *
+ * patches_dev is a DEVICE array of npatch gd_patch records (owned by the
+ * caller, read by the kernels at every launch -- so a captured graph reads
+ * the records current at each replay); 1 <= npatch <= 65536, else GD_E_ARG.
+ * Buffers, offsets and dt_dev as in godunov_step_batched; bflux_base may be
+ * NULL. Results are bitwise those of godunov_step_batched (FP64 runs on 16x8
+ * tiles, FP32 on 24x8 tiles, z-ranges of up to 32 planes). PLM limiters only
+ * (GD_E_UNSUPPORTED for PPM); GD_GHOSTED only.
+ *
+ * Checks: the host checks opts, npatch, gamma and the pointers before
+ * anything is launched (errors in gd_last_error(NULL)). The descriptors are
+ * on the device, so the host cannot see them: a plan kernel checks each
+ * record (extents 1..16384, 2 <= ng <= 64, dx > 0, dt >= 0 when dt_dev is
+ * NULL, offsets >= 0, plane size below 2^31) and skips a failing patch,
+ * whose output and flux blocks are then left untouched. Offsets beyond the
+ * caller's buffers and overlapping blocks cannot be detected: the caller
+ * must get them right, as the Python binding does with the host copy of
+ * the table.
+ *
+ * Every call on a device shares that device's array (each call's first
+ * launch clears what must start at zero): two calls in flight together on
+ * one device, on the same or different streams, race; serialise them. */
+int godunov_step_batched_noalloc(const gd_opts *opts, int npatch, const gd_patch *patches_dev,
+                                 const void *u_in_base, void *u_out_base, void *bflux_base,
+                                 const double *dt_dev, double gamma, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgodunov.so")
 SOURCES = ["godunov_kernels.hip", "godunov_adjoint.hip", "godunov_mhd.hip", "godunov_amr.hip",
-           "godunov_ppm.hip", "godunov_api.cpp"]
+           "godunov_ppm.hip", "godunov_noalloc.hip", "godunov_api.cpp"]
 ARCH = os.environ.get("GODUNOV_ARCH", "gfx950")
 
 

@@ -63,6 +63,21 @@ struct Slot {
 
 }  // namespace
 
+namespace gd {
+
+int set_call_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_create_error = buf;
+    return code;
+}
+
+}  // namespace gd
+
 struct gd_stream_state;                  // the streamed-batch pipeline (below)
 static void free_stream_state(gd_stream_state *st);
 

@@ -171,6 +171,10 @@ int launch_amr_seam(int dtype, int limiter, int riemann, const AmrTables &t, con
                     const Scalars &sc, double dx_coarse, double dt, const double *dt_dev,
                     hipStream_t s);
 
+// Record the message of a failing call that has no context (the text
+// gd_last_error(NULL) returns on this thread); returns code.
+int set_call_error(int code, const char *fmt, ...);
+
 // *dst = v, stream-ordered (capturable, unlike a host-to-device copy).
 int launch_set_scalar(double *dst, double v, hipStream_t s);
 

@@ -80,7 +80,7 @@ EXPORTS = ("gd_create", "gd_destroy", "gd_last_error", "gd_get_stats", "gd_reset
            "gd_autotune_step", "gd_autotune_batched", "gd_get_config", "gd_set_config",
            "godunov_step_cfl", "godunov_step_batched_cfl", "godunov_step_mhd", "godunov_step_mhd_cfl",
            "cfl_dt_mhd", "gd_amr_create", "gd_amr_destroy", "gd_amr_fill_ghosts", "gd_amr_reflux",
-           "gd_amr_step", "godunov_step_batched_streamed")
+           "gd_amr_step", "godunov_step_batched_streamed", "godunov_step_batched_noalloc")
 
 _lib = None
 _lock = threading.Lock()
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.gd_amr_step.argtypes = [vp, vp, P(gd_opts), vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
         lib.godunov_step_batched_streamed.argtypes = [vp, P(gd_opts), i32, vp, vp, vp, vp, vp, dbl,
                                                       ctypes.c_size_t, vp]
+        lib.godunov_step_batched_noalloc.argtypes = [P(gd_opts), i32, vp, vp, vp, vp, vp, dbl, vp]
         for name in EXPORTS:
             if name != "gd_last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -384,6 +385,52 @@ def step_batched_streamed(u_in, table, gamma, *, out, bflux=None, chunk_bytes=25
         ctx.handle, ctypes.byref(o), len(table), table.ctypes.data, _ptr(u_in), _ptr(out),
         _ptr(bflux), _ptr(dt_dev), float(gamma), int(chunk_bytes), _stream(stream)))
     return out, bflux
+
+
+NOALLOC_MAX_PATCHES = 65536
+
+
+def step_batched_noalloc(u_in, patches_dev, npatch, gamma, *, out, bflux=None, dt_dev=None,
+                         table=None, limiter="minmod", riemann="hllc", rho_floor=RHO_FLOOR,
+                         p_floor=P_FLOOR, stream=None):
+    """godunov_step_batched_noalloc: the batched step with no allocation by
+    the library. patches_dev is a uint8 CUDA tensor holding npatch gd_patch
+    records (e.g. device_table(table)); the kernels read it at every launch.
+    Give the host table too (table=) to have the buffers checked against its
+    offsets; the library cannot see the device records on the host."""
+    _check_tensor(u_in, "u_in")
+    _check_tensor(out, "out", u_in.dtype)
+    if bflux is not None:
+        _check_tensor(bflux, "bflux", u_in.dtype)
+    _check_tensor(patches_dev, "patches_dev", torch.uint8)
+    _check_size(patches_dev, "patches_dev", int(npatch) * PATCH_DTYPE.itemsize)
+    if patches_dev.device != u_in.device:
+        raise ValueError("patches_dev must be on the device of u_in")
+    if dt_dev is not None:
+        _check_scalar(dt_dev, "dt_dev")
+    if table is not None:
+        table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+        if len(table) != npatch:
+            raise ValueError("table and npatch disagree")
+        _check_batch(table, u_in, out, bflux)
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the Godunov library has no CPU path")
+    o = _opts(u_in.dtype, False, limiter, riemann, rho_floor, p_floor)
+    with torch.cuda.device(u_in.device):
+        r = lib.godunov_step_batched_noalloc(ctypes.byref(o), int(npatch), _ptr(patches_dev),
+                                             _ptr(u_in), _ptr(out), _ptr(bflux), _ptr(dt_dev),
+                                             float(gamma), _stream(stream))
+    if r != GD_OK:
+        raise GodunovError(r, lib.gd_last_error(None).decode())
+    return out, bflux
+
+
+def device_table(table, device=None) -> torch.Tensor:
+    """The gd_patch records of a host table as a uint8 CUDA tensor."""
+    table = np.ascontiguousarray(table, dtype=PATCH_DTYPE)
+    return torch.from_numpy(table.view(np.uint8).copy()).to(
+        torch.device("cuda", torch.cuda.current_device() if device is None else device))
 
 
 def cfl_dt_batched(u_in, table, gamma, cfl=0.5, *, out=None, rho_floor=RHO_FLOOR,

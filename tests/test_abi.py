@@ -298,3 +298,20 @@ def test_batch_extents_cover_the_packed_layout():
     with pytest.raises(ValueError):
         godunov._check_size(torch.empty(3), "x", 0, (4,))
     assert np.all(t["nx"] >= 1)
+
+
+def test_noalloc_step_checks_its_arguments_on_the_host(lib):
+    """The allocation-free batched step rejects bad options, a patch count
+    beyond its static scratch and NULL pointers before touching a device."""
+    cases = [(_opts(), 0, 1, 1, -1), (_opts(), 65537, 1, 1, -1), (_opts(), 4, 0, 1, -1),
+             (_opts(), 4, 1, 0, -1), (_opts(bc=1), 4, 1, 1, -4), (_opts(limiter=3), 4, 1, 1, -4),
+             (_opts(dtype=5), 4, 1, 1, -1)]
+    for opts, npatch, pd, u, expect in cases:
+        r = lib.godunov_step_batched_noalloc(ctypes.byref(opts), npatch, ctypes.c_void_p(pd),
+                                             ctypes.c_void_p(u), ctypes.c_void_p(u + 0x10000 if u else 0),
+                                             None, None, 5 / 3, None)
+        assert r == expect, (npatch, pd, u, r)
+        assert lib.gd_last_error(None)
+    r = lib.godunov_step_batched_noalloc(None, 4, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                         ctypes.c_void_p(2), None, None, 5 / 3, None)
+    assert r == -1
