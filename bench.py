@@ -45,8 +45,10 @@ METRIC = "Mcell-updates/s per Godunov step (plain vs batched), % HBM roofline; a
 # the step kernel's own code (its launch interface lives in godunov_internal.h,
 # whose other declarations do not change the kernel)
 KERNEL_SRC = [os.path.join(ROOT, "paper_1412_0934_amd", "csrc", f)
-              for f in ("godunov_kernels.hip", "godunov_cell.h", "godunov_math.h")]
+              for f in ("godunov_kernels.hip", "godunov_tile.h", "godunov_cell.h",
+                        "godunov_math.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "step_kernel_periodic256_valu.txt")
 
 
 def kernel_source_hash() -> str:
@@ -57,16 +59,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tile_config):
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary, if it was taken on the current kernel source and holds a
-    measurement for this tile configuration; else None. The summary has one
-    block of "key: value" lines per configuration, each opened by its
-    tile_config line."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def _summary_blocks(path):
+    """The "key: value" blocks of a committed counter summary, each opened
+    by its tile_config line."""
+    if not os.path.exists(path):
+        return []
     blocks, cur = [], None
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" not in line or line.startswith("#"):
             continue
         k, v = (x.strip() for x in line.split(":", 1))
@@ -74,15 +73,46 @@ def measured_traffic(tile_config):
             cur = {}
             blocks.append(cur)
         if cur is not None:
-            cur[k] = v
-    for b in blocks:
+            cur[k] = v.split("  (")[0].strip()
+    return blocks
+
+
+def _current_block(path, tile_config):
+    """The summary block for this tile configuration taken on the current
+    kernel source, or None (the figures then describe another kernel)."""
+    for b in _summary_blocks(path):
         if (b.get("tile_config") == tile_config and
                 b.get("kernel_source_sha256_16") == kernel_source_hash()):
-            try:
-                return float(b["hbm_bytes_per_launch"])
-            except (KeyError, ValueError):
-                return None
+            return b
     return None
+
+
+def measured_traffic(tile_config):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, if it was taken on the current kernel source and holds a
+    measurement for this tile configuration; else None."""
+    b = _current_block(TRAFFIC_FILE, tile_config)
+    try:
+        return float(b["hbm_bytes_per_launch"]) if b else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu(tile_config):
+    """VALU wave-instructions per cell and the fraction of SIMD cycles that
+    issue VALU work, from the committed counter summary of the current
+    kernel source and tile configuration; else None."""
+    b = _current_block(VALU_FILE, tile_config)
+    if not b:
+        return None
+    try:
+        return {"valu_wave_instructions_per_cell": float(b["valu_wave_instructions_per_cell"]),
+                "fp64_valu_wave_instructions_per_cell":
+                    float(b["fp64_valu_wave_instructions_per_cell"]),
+                "simd_valu_issue_fraction": float(b["simd_valu_issue_fraction"]),
+                "source": os.path.relpath(VALU_FILE, ROOT)}
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -131,6 +161,8 @@ def bench_periodic(torch, gd, steps, warmup, n=256, tile=None, zlen=None):
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
     torch.cuda.synchronize()
+    ctx = gd.context()
+    ctx.reset_stats()
     log(f"bench: timing {steps} steps")
     t0 = time.perf_counter()
     for i in range(steps):
@@ -140,6 +172,7 @@ def bench_periodic(torch, gd, steps, warmup, n=256, tile=None, zlen=None):
             one_step(ub, ua, events[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    floor_hits = ctx.floor_hits()
     per_step = [a.elapsed_time(b) for a, b in events]
     kernel_ms = sum(per_step) / steps
     log("bench: step kernel ms, first 5 / min / median / max: "
@@ -149,6 +182,7 @@ def bench_periodic(torch, gd, steps, warmup, n=256, tile=None, zlen=None):
     return {
         "cells": cells, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
         "step_kernel_ms": kernel_ms, "bytes_per_launch": 80.0 * cells, "u0": u0,
+        "floor_hits": floor_hits,
     }
 
 
@@ -677,6 +711,18 @@ def cpu_single_thread(u0):
             "sample": f"1 full step (cfl + step) of the same {n}^3 box, {el:.1f} s"}
 
 
+def cpu_description():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline(u0, budget_s=12.0, max_steps=40):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -685,18 +731,123 @@ def cpu_baseline(u0, budget_s=12.0, max_steps=40):
     log(f"bench: CPU oracle on {threads} threads")
     u = u0
     steps = 0
+    floor_hits = None
     t0 = time.perf_counter()
     while steps < max_steps:
         dt = oracle.cfl_dt(u, GAMMA, dx, 0.5, periodic=True)
-        u = oracle.step(u, GAMMA, dx, dt, periodic=True)[0]
+        u, _, hits = oracle.step(u, GAMMA, dx, dt, periodic=True)
+        if floor_hits is None:
+            floor_hits = int(hits)
         steps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
     return {"value": round(steps * n ** 3 / el / 1e6, 3), "unit": "Mcell-updates/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "kind": "oracle", **cpu_description(),
             "sample": f"{steps} full steps (cfl + step) of the same {n}^3 periodic box, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "oracle_floor_hits_first_step": floor_hits}
+
+
+def _in_child(code, threads, timeout=300):
+    """Run `code` in a fresh interpreter with OMP_NUM_THREADS = threads and
+    return the float it prints last (or None)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=timeout)
+    if r.returncode != 0:
+        log(r.stderr[-2000:])
+        return None
+    return float(r.stdout.strip().splitlines()[-1])
+
+
+_BATCH_CODE = """
+import sys, time
+import numpy as np
+sys.path.insert(0, %r)
+import oracle
+z = np.load(%r)
+u_in, dims, off, dx = z["u_in"], z["dims"], z["u_in_off"], z["dx"]
+npatch, g = %d, %r
+def patch(p):
+    nx, ny, nz = (int(v) for v in dims[p])
+    n = 5 * (nz + 4) * (ny + 4) * (nx + 4)
+    return u_in[off[p]:off[p] + n].reshape(5, nz + 4, ny + 4, nx + 4)
+dt = 0.5 * min(dx[p] / oracle.max_signal(patch(p), g) for p in range(len(dims)))
+t0 = time.perf_counter()
+for p in range(npatch):
+    oracle.step(patch(p), g, dx[p], dt)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_batched(threads_all):
+    """The oracle's step of the 4096-patch batch (its patches one after
+    another, each with the oracle's OpenMP loops): the whole batch on all
+    host threads, the first 512 patches on one thread."""
+    import tempfile
+    from paper_1412_0934_amd import inputs
+    b = bench_batched.cache or inputs.amr_batch(4096, seed=5)
+    cells = np.prod(b.dims, axis=1)
+    out = {"workload": "4096 ghost-zoned patches 8^3..32^3, one step (cfl dt, minmod + HLLC, "
+                       "bflux)", "unit": "Mcell-updates/s", "kind": "oracle"}
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "batch.npz")
+        np.savez(path, u_in=b.u_in, dims=b.dims, u_in_off=b.u_in_off, dx=b.dx)
+        for key, threads, npatch in (("all_threads", threads_all, b.npatch),
+                                     ("single_thread", 1, 512)):
+            log(f"bench: CPU oracle, batched, {npatch} patches on {threads} threads")
+            el = _in_child(_BATCH_CODE % (ROOT, path, npatch, GAMMA), threads)
+            if el is not None:
+                c = int(cells[:npatch].sum())
+                out[key] = {"value": round(c / el / 1e6, 3), "cores": threads,
+                            "sample": f"{npatch} patches, {c} cells, {el:.2f} s"}
+    return out
+
+
+_GRAD_CODE = """
+import sys, time
+import numpy as np
+sys.path.insert(0, %r)
+import oracle
+from paper_1412_0934_amd import inputs
+n, nsteps, every = %d, 20, 5
+U0, target = inputs.smooth_box(n)
+dx = 1.0 / n
+dt = oracle.cfl_dt(U0, %r, dx, 0.5, periodic=True)
+t0 = time.perf_counter()
+ckpt, u = [U0], U0
+for k in range(nsteps):
+    u = oracle.step(u, %r, dx, dt, periodic=True)[0]
+    if (k + 1) %% every == 0 and k + 1 < nsteps:
+        ckpt.append(u)
+lam = np.zeros_like(U0)
+lam[0] = 2 * (u[0] - target)
+for seg in reversed(range(len(ckpt))):
+    states = [ckpt[seg]]
+    for _ in range(every - 1):
+        states.append(oracle.step(states[-1], %r, dx, dt, periodic=True)[0])
+    for s in reversed(states):
+        lam = oracle.step_adjoint(s, lam, %r, dx, dt, periodic=True)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_gradient(threads_all):
+    """The oracle's gradient of the 20-step rollout (checkpoints every 5,
+    segments recomputed, loss sum (rho_T - rho_target)^2) on the smooth
+    periodic box: 64^3 on all host threads, 32^3 on one thread (the GPU
+    figure, also.adjoint, is for 128^3: 8 times the cells of 64^3)."""
+    out = {"workload": "gradient of a 20-step rollout of the smooth periodic box (checkpoints "
+                       "every 5): 20 forward + 16 recomputed + 20 adjoint steps",
+           "unit": "s per gradient", "kind": "oracle"}
+    for key, threads, n in (("all_threads", threads_all, 64), ("single_thread", 1, 32)):
+        log(f"bench: CPU oracle gradient, {n}^3 on {threads} threads")
+        el = _in_child(_GRAD_CODE % (ROOT, n, GAMMA, GAMMA, GAMMA, GAMMA), threads)
+        if el is not None:
+            out[key] = {"value": round(el, 3), "cores": threads, "box": f"{n}^3"}
+    return out
 
 
 def main():
@@ -776,7 +927,9 @@ def main():
             "kernel": "step_kernel<double, minmod, HLLC>", "step_kernel_ms": round(r["step_kernel_ms"], 4),
             "tile_config": gd.get_config(torch.float64),
             "algorithmic_bytes_per_launch": r["bytes_per_launch"],
+            "valu": measured_valu(f"{cfg['shape_single']}/{cfg['zlen_single']}"),
         },
+        "floor_hits_per_step": r["floor_hits"] / args.steps,
     }
     also = {}
     if not args.no_sod:
@@ -808,6 +961,9 @@ def main():
         single = cpu_single_thread(r["u0"])
         if single is not None:
             line["cpu_baseline"]["single_thread"] = single
+        threads = line["cpu_baseline"]["cores"]
+        line["cpu_baseline"]["batched"] = cpu_batched(threads)
+        line["cpu_baseline"]["gradient"] = cpu_gradient(threads)
     line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
