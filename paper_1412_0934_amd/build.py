@@ -34,14 +34,27 @@ def flags() -> list[str]:
     ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    objs = []
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (each flag applies
+# to the host compilation only; the device code is built as always). The
+# runtime is clang's, loaded with LD_PRELOAD by the process that uses the
+# library.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, jobs: int = 4, sanitize: bool = False, out: str = None) -> str:
+    """Compile every source for gfx950 and link libgodunov.so (or `out`).
+    sanitize=True instruments the host code (argument checks, tables,
+    dispatch) with ASan and UBSan, in a build folder of its own."""
+    build_dir = BUILD + ("_san" if sanitize else "")
+    lib = out or LIB
+    os.makedirs(build_dir, exist_ok=True)
+    extra = SANITIZE_HOST if sanitize else []
 
     def compile_one(src):
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc()] + lang + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + lang + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
@@ -49,13 +62,15 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    tmp = lib + ".tmp"
+    link_extra = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-shared-libsan"] if sanitize else []
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + link_extra + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -30,7 +30,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgodunov.so")
+# the library to load: the in-tree build, or another build of the same
+# sources named by GODUNOV_LIB (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("GODUNOV_LIB", os.path.join(_HERE, "libgodunov.so"))
 
 GD_OK, GD_E_ARG, GD_E_HIP, GD_E_NOMEM, GD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 DTYPES = {torch.float64: 0, torch.float32: 1}

@@ -8,7 +8,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "godunov.h")
-LIB = os.path.join(ROOT, "paper_1412_0934_amd", "libgodunov.so")
+LIB = os.environ.get("GODUNOV_LIB", os.path.join(ROOT, "paper_1412_0934_amd", "libgodunov.so"))
 
 
 def declared_functions():
