@@ -32,19 +32,21 @@ _LIB = os.path.join(_LIB_DIR, "liboracle.so")
 _LIB_CS = os.path.join(_LIB_DIR, "liboracle_cs.so")
 _LIB_PPM = os.path.join(_LIB_DIR, "libppm_oracle.so")
 
-LIMITERS = {"minmod": 0, "mc": 1, "none": 2, "unlimited": 2, "ppm": 3, "ppm_unlimited": 4}
-PPM = ("ppm", "ppm_unlimited")
+LIMITERS = {"minmod": 0, "mc": 1, "none": 2, "unlimited": 2, "ppm": 3, "ppm_unlimited": 4,
+            "ppm_ct": 5, "ppm_ct_unlimited": 6}
+PPM = ("ppm", "ppm_unlimited", "ppm_ct", "ppm_ct_unlimited")
 RIEMANN = {"hllc": 0, "hll": 1}
 RHO_FLOOR = 1e-10
 P_FLOOR = 1e-10
 
 
 def build(verbose: bool = False, src_dir: str = _HERE, out_dir: str = _HERE,
-          extra_flags=()) -> None:
-    """Compile the oracle libraries with gcc (plain C11 + OpenMP). The default
-    build has no FMA contraction (x86-64-v2); extra_flags (e.g. "-mfma",
-    "-ffp-contract=fast") give another valid rounding of the same arithmetic."""
-    common = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v2",
+          extra_flags=(), cc: str = "gcc") -> None:
+    """Compile the oracle libraries (plain C11 + OpenMP, gcc by default). The
+    default build has no FMA contraction (x86-64-v2); extra_flags (e.g.
+    "-mfma", "-ffp-contract=fast") give another valid rounding of the same
+    arithmetic, or sanitizer instrumentation."""
+    common = [cc, "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v2",
               *extra_flags]
     cmds = [
         common + ["-o", os.path.join(out_dir, "liboracle.so"),
@@ -122,7 +124,22 @@ def _lib_ppm() -> ctypes.CDLL:
     lib.orc_step_ppm.restype = ctypes.c_long
     lib.orc_ppm_edges.argtypes = [ctypes.c_int, dp, dp, dp]
     lib.orc_ppm_edges.restype = None
+    lib.orc_ppm_trace.argtypes = [P, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.orc_ppm_trace.restype = None
     return lib
+
+
+def ppm_trace(W, aL, aR, d, upper, gamma, dx, dt):
+    """The characteristically traced state on the upper (upper=True) or lower
+    face along axis d of a cell with primitive state W and parabola edges
+    aL, aR (five primitives each), before the transverse terms."""
+    P = _Problem(1, 1, 1, 3, 1, LIMITERS["ppm_ct"], 0, float(gamma), float(dx), float(dt),
+                 RHO_FLOOR, P_FLOOR)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (W, aL, aR)]
+    out = np.empty(5)
+    _lib_ppm().orc_ppm_trace(ctypes.byref(P), *(a.ctypes.data for a in arrs), int(d), int(upper),
+                             out.ctypes.data)
+    return out
 
 
 def ppm_edges(a5, limiter="ppm"):

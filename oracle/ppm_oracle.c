@@ -31,10 +31,32 @@
  *   5. face states W*_i + (a_R,i - W_i) on the upper face along d and
  *      W*_i + (a_L,i - W_i) on the lower face, floored. With a_R,L = W +- S/2
  *      these are the PLM face states.
- * Characteristic tracing (Colella & Woodward's time averaging over the
- * domains of dependence) is replaced by this half step, which couples all
- * three axes as the unsplit PLM step does; no contact steepening and no
- * flattening.
+ * No contact steepening and no flattening.
+ *
+ * With characteristic tracing (limiter GD_PPM_CT, or GD_PPM_CT_UNLIMITED with
+ * the unlimited parabola), steps 4 and 5 become, per axis d and cell:
+ *   4'. the waves of the primitive system along d at the cell's state,
+ *       speeds u_d - c, u_d (entropy and the two shear waves), u_d + c, with
+ *       Courant numbers s = speed dt/dx; for the upper face, each wave with
+ *       s > 0 contributes l . (A(s) - a_R) r, where A(s) is the average of
+ *       the parabola over the last s of the cell (Colella & Woodward's
+ *       domain of dependence of the face over the half step's time average),
+ *         A(s) - a_R = -(s/2) (a_R - a_L - (1 - 2s/3) a_6),
+ *         a_6 = 6 (a - (a_L + a_R)/2),
+ *       and l, r the left and right eigenvectors of the wave; the face state
+ *       is a_R plus these contributions (for the lower face, waves with
+ *       s < 0 over the first |s| of the cell, with
+ *         A(s) - a_L = (|s|/2) (a_R - a_L + (1 - 2|s|/3) a_6));
+ *       eigenvectors in (rho, u_n, u_t1, u_t2, p):
+ *         r_-+ = (1, -+c/rho, 0, 0, c^2), l_-+ = (0, -+rho/(2c), 0, 0, 1/(2c^2)),
+ *         entropy r = l' = (1, 0, 0, 0, 0) with l = (1, 0, 0, 0, -1/c^2),
+ *         shear r = l = the unit vectors of u_t1 and u_t2;
+ *   5'. plus the transverse terms of the Hancock half step,
+ *       -dt/(2dx) sum_{d' != d} A_d'(W) (a_R,d' - a_L,d'), then floored.
+ * The reference state is the edge value, not the average over the fastest
+ * wave's domain: a face state then changes continuously when a wave speed
+ * crosses zero. For a linear profile with every wave moving towards the
+ * face the traced state is the Hancock state W* + S_d/2.
  *
  * The stencil: the cells whose face states some face needs are the interior
  * and the face ghosts of depth 1; each reads two cells either side along
@@ -43,7 +65,15 @@
  */
 #include "godunov_oracle.c"
 
-enum { LIM_PPM = 3, LIM_PPM_NONE = 4 };
+enum { LIM_PPM = 3, LIM_PPM_NONE = 4, LIM_PPM_CT = 5, LIM_PPM_CT_NONE = 6 };
+
+/* The parabola construction of a limiter value: limited or unlimited. */
+static int ppm_parabola(int limiter)
+{
+    return limiter == LIM_PPM_NONE || limiter == LIM_PPM_CT_NONE ? LIM_PPM_NONE : LIM_PPM;
+}
+
+static int ppm_traced(int limiter) { return limiter == LIM_PPM_CT || limiter == LIM_PPM_CT_NONE; }
 
 /* Work arrays cover the interior plus three layers: index in [-3, n+3). */
 static size_t ext3_index(const ext_box *b, int i, int j, int k)
@@ -114,12 +144,52 @@ static void ppm_edges(int limiter, real amm, real am, real a0, real ap, real app
     *aR = r;
 }
 
+/* The parabola's average over the last s of the cell minus a_R (upper edge,
+ * s > 0) or over the first |s| of the cell minus a_L (lower edge, s < 0). */
+static real ppm_average_minus_edge(real aL, real aR, real a0, real s, int upper)
+{
+    real da = aR - aL, a6 = 6.0 * (a0 - 0.5 * (aL + aR));
+    if (upper) return -0.5 * s * (da - (1.0 - 2.0 * s / 3.0) * a6);
+    real t = -s;
+    return 0.5 * t * (da + (1.0 - 2.0 * t / 3.0) * a6);
+}
+
+/* Step 4': the traced state on the upper (upper = 1) or lower face of a
+ * cell along d, before the transverse terms. */
+static void ppm_trace(const orc_problem *P, const real W[5], const real aL[5], const real aR[5],
+                      int d, int upper, real out[5])
+{
+    int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+    real rho = W[0], p = W[4], un = W[n];
+    real c = r_sqrt(P->gamma * p / rho);
+    real cfl = P->dt / P->dx;
+    real s[3] = { (un - c) * cfl, un * cfl, (un + c) * cfl };
+    for (int q = 0; q < 5; q++) out[q] = upper ? aR[q] : aL[q];
+    for (int w = 0; w < 3; w++) {
+        if (upper ? !(RE(s[w]) > 0.0) : !(RE(s[w]) < 0.0)) continue;
+        real D[5];
+        for (int q = 0; q < 5; q++) D[q] = ppm_average_minus_edge(aL[q], aR[q], W[q], s[w], upper);
+        if (w == 1) {
+            /* entropy and shear waves */
+            out[0] += D[0] - D[4] / (c * c);
+            out[t1] += D[t1];
+            out[t2] += D[t2];
+        } else {
+            real sg = w == 0 ? -1.0 : 1.0;
+            real beta = sg * rho / (2.0 * c) * D[n] + D[4] / (2.0 * c * c);
+            out[0] += beta;
+            out[n] += sg * c / rho * beta;
+            out[4] += c * c * beta;
+        }
+    }
+}
+
 static int check_ppm_problem(const orc_problem *P)
 {
     if (P->nx < 1 || P->ny < 1 || P->nz < 1) return -1;
     if (!P->periodic && P->ng < 3) return -1;
     if (!(P->gamma > 1.0) || !(P->dx > 0.0) || !(P->dt >= 0.0)) return -1;
-    if (P->limiter != LIM_PPM && P->limiter != LIM_PPM_NONE) return -1;
+    if (P->limiter < LIM_PPM || P->limiter > LIM_PPM_CT_NONE) return -1;
     if (P->riemann < 0 || P->riemann > 1) return -1;
     return 0;
 }
@@ -178,14 +248,32 @@ long API(orc_step_ppm)(const orc_problem *P, const real *u_in, real *u_out, real
                     size_t cpp = ext3_index(&B, i + 2 * di, j + 2 * dj, k + 2 * dk);
                     for (int q = 0; q < 5; q++) {
                         real aL, aR;
-                        ppm_edges(P->limiter, W[5 * cmm + q], W[5 * cm + q], W[5 * c + q],
-                                  W[5 * cp + q], W[5 * cpp + q], &aL, &aR);
+                        ppm_edges(ppm_parabola(P->limiter), W[5 * cmm + q], W[5 * cm + q],
+                                  W[5 * c + q], W[5 * cp + q], W[5 * cpp + q], &aL, &aR);
                         e[10 * d + q] = aL;
                         e[10 * d + 5 + q] = aR;
                         s[d][q] = aR - aL;
                     }
                 }
                 hancock_predictor(P, W + 5 * c, s, Ws + 5 * c);
+                if (ppm_traced(P->limiter)) {
+                    /* steps 4' and 5': the six traced face states, stored in
+                     * place of the edges (FS[d][side]: lower, upper) */
+                    real fs[3][2][5];
+                    for (int d = 0; d < 3; d++) {
+                        real st[3][5], Wt[5];
+                        for (int dd = 0; dd < 3; dd++)
+                            for (int q = 0; q < 5; q++) st[dd][q] = dd == d ? 0.0 : s[dd][q];
+                        hancock_predictor(P, W + 5 * c, st, Wt);
+                        for (int side = 0; side < 2; side++) {
+                            ppm_trace(P, W + 5 * c, e + 10 * d, e + 10 * d + 5, d, side, fs[d][side]);
+                            for (int q = 0; q < 5; q++) fs[d][side][q] += Wt[q] - W[5 * c + q];
+                        }
+                    }
+                    for (int d = 0; d < 3; d++)
+                        for (int side = 0; side < 2; side++)
+                            for (int q = 0; q < 5; q++) e[10 * d + 5 * side + q] = fs[d][side][q];
+                }
             }
 
     /* face states and one flux per face; face (i'-1/2) along d lies between
@@ -201,8 +289,13 @@ long API(orc_step_ppm)(const orc_problem *P, const real *u_in, real *u_out, real
                     size_t cl = ext3_index(&B, li, lj, lk), cr = ext3_index(&B, i, j, k);
                     real WL[5], WR[5];
                     for (int q = 0; q < 5; q++) {
-                        WL[q] = Ws[5 * cl + q] + (E[30 * cl + 10 * d + 5 + q] - W[5 * cl + q]);
-                        WR[q] = Ws[5 * cr + q] + (E[30 * cr + 10 * d + q] - W[5 * cr + q]);
+                        if (ppm_traced(P->limiter)) {
+                            WL[q] = E[30 * cl + 10 * d + 5 + q];
+                            WR[q] = E[30 * cr + 10 * d + q];
+                        } else {
+                            WL[q] = Ws[5 * cl + q] + (E[30 * cl + 10 * d + 5 + q] - W[5 * cl + q]);
+                            WR[q] = Ws[5 * cr + q] + (E[30 * cr + 10 * d + q] - W[5 * cr + q]);
+                        }
                     }
                     floor_state(P, WL, &hits);
                     floor_state(P, WR, &hits);
@@ -261,6 +354,15 @@ long API(orc_step_ppm)(const orc_problem *P, const real *u_in, real *u_out, real
 
     free(W); free(E); free(Ws); free(Fx); free(Fy); free(Fz);
     return hits;
+}
+
+/* Step 4' for one cell, exposed for the tests: W the cell's primitive state,
+ * aL, aR the parabola edges of its five primitives along axis d, upper = 1
+ * for the upper face; P supplies gamma, dt and dx. */
+void API(orc_ppm_trace)(const orc_problem *P, const real *W, const real *aL, const real *aR,
+                        int d, int upper, real *out)
+{
+    ppm_trace(P, W, aL, aR, d, upper, out);
 }
 
 /* Edge values of one parabola, exposed for the tests. */

@@ -105,6 +105,20 @@ MUTATIONS = [
      "right face state offset sign"),
     (PPMF, "size_t cpp = ext3_index(&B, i + 2 * di, j + 2 * dj, k + 2 * dk);",
      "size_t cpp = ext3_index(&B, i + di, j + dj, k + dk);", "PPM stencil's far right cell"),
+    (PPMF, "return -0.5 * s * (da - (1.0 - 2.0 * s / 3.0) * a6);",
+     "return -0.5 * s * (da - (1.0 - s / 3.0) * a6);", "tracing: upper average's curvature weight"),
+    (PPMF, "return 0.5 * t * (da + (1.0 - 2.0 * t / 3.0) * a6);",
+     "return 0.5 * t * (da - (1.0 - 2.0 * t / 3.0) * a6);", "tracing: lower average's curvature sign"),
+    (PPMF, "out[n] += sg * c / rho * beta;", "out[n] += sg * rho / c * beta;",
+     "tracing: acoustic eigenvector's velocity component"),
+    (PPMF, "if (upper ? !(RE(s[w]) > 0.0) : !(RE(s[w]) < 0.0)) continue;",
+     "if (upper ? !(RE(s[w]) > -1.0) : !(RE(s[w]) < 1.0)) continue;",
+     "tracing: waves moving away from the face included"),
+    (PPMF, "for (int q = 0; q < 5; q++) fs[d][side][q] += Wt[q] - W[5 * c + q];",
+     "for (int q = 0; q < 5; q++) fs[d][side][q] += 0.0 * (Wt[q] - W[5 * c + q]);",
+     "tracing: transverse terms dropped"),
+    (PPMF, "out[0] += D[0] - D[4] / (c * c);", "out[0] += D[0] + D[4] / (c * c);",
+     "tracing: entropy wave's pressure weight"),
 ]
 
 
