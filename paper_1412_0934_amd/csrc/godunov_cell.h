@@ -31,19 +31,27 @@ __device__ __forceinline__ Phys<T> make_phys(const Scalars &sc)
 
 // ------------------------------------------------------------ cell physics
 
+// max(x, floor), counting a raise. Written as a comparison and a select that
+// share the comparison with the count: a maximum of a loaded value costs two
+// extra canonicalising instructions in IEEE mode. Equal to fmax for every
+// number x; a NaN x stays NaN.
+template <typename T>
+__device__ __forceinline__ T floored(T x, T floor, int &hits)
+{
+    const bool below = x < floor;
+    hits += below;
+    return below ? floor : x;
+}
+
 template <typename T>
 __device__ __forceinline__ void prim_from_cons(const T U[5], T W[5], T &inv_rho,
                                                const Phys<T> &ph, int &hits)
 {
-    T rho = U[0];
-    hits += rho < ph.rho_floor;
-    rho = fmax(rho, ph.rho_floor);
+    const T rho = floored(U[0], ph.rho_floor, hits);
     T inv = fast_rcp(rho);
     T u = U[1] * inv, v = U[2] * inv, w = U[3] * inv;
     T kin = T(0.5) * (U[1] * u + U[2] * v + U[3] * w);
-    T p = ph.gm1 * (U[4] - kin);
-    hits += p < ph.p_floor;
-    p = fmax(p, ph.p_floor);
+    const T p = floored(ph.gm1 * (U[4] - kin), ph.p_floor, hits);
     W[0] = rho; W[1] = u; W[2] = v; W[3] = w; W[4] = p;
     inv_rho = inv;
 }
@@ -88,10 +96,8 @@ __device__ __forceinline__ void face_state(const T Ws[5], const T S[5], T half_s
 {
 #pragma unroll
     for (int q = 0; q < 5; ++q) out[q] = Ws[q] + half_sign * S[q];
-    hits += out[0] < ph.rho_floor;
-    hits += out[4] < ph.p_floor;
-    out[0] = fmax(out[0], ph.rho_floor);
-    out[4] = fmax(out[4], ph.p_floor);
+    out[0] = floored(out[0], ph.rho_floor, hits);
+    out[4] = floored(out[4], ph.p_floor, hits);
 }
 
 // ------------------------------------------------------------ Riemann fluxes
@@ -130,16 +136,17 @@ __device__ __forceinline__ void hllc_rotated(const T L[5], const T R[5], const P
     // U*_K = a (1, S*, v_K, w_K, e) with a = rho_K (S_K - u_K)/(S_K - S*) and
     // e = E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))); the energy
     // component a e is expanded so that only 1/(S_K - S*) is needed.
+    // F = F_K + s (U*_K - U_K) with s = S_K in the star regions and 0 in the
+    // upwind ones, where 1/(S_K - S*) is replaced by 0 so that U*_K stays
+    // finite: two selects instead of one per component, the same value.
     T dK = SK - uK;
-    T inv_d = fast_rcp(SK - Sst);
+    T inv_d = star ? fast_rcp(SK - Sst) : T(0);
+    T sK = star ? SK : T(0);
     T a = rK * dK * inv_d;
     T su = Sst - uK;
     T Us[5] = { a, a * Sst, a * vK, a * wK, inv_d * (EK * dK + su * pK) + a * Sst * su };
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        T Fs = FK[q] + SK * (Us[q] - UK[q]);
-        F[q] = star ? Fs : FK[q];
-    }
+    for (int q = 0; q < 5; ++q) F[q] = FK[q] + sK * (Us[q] - UK[q]);
 }
 
 template <typename T>
