@@ -433,12 +433,13 @@ def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
             "ghost_fill_gbs": round(fill_bytes / (stage_ms["ghost_fill"] * 1e-3) / 1e9, 1)}
 
 
-def bench_ppm(torch, gd, u0, steps=10, warmup=2):
+def bench_ppm(torch, gd, u0, steps=10, warmup=2, limiter="ppm"):
     """The 256^3 periodic box with the PPM reconstruction (limited parabola,
     HLLC): per step one godunov_step_cfl (predict and update launches, then
-    the CFL reduction of the new state), dt in a device scalar."""
+    the CFL reduction of the new state), dt in a device scalar; with the
+    Hancock half step (limiter "ppm") or characteristic tracing ("ppm_ct")."""
     n = u0.shape[1]
-    log(f"bench: PPM, {n}^3 periodic box")
+    log(f"bench: PPM ({limiter}), {n}^3 periodic box")
     dx = 1.0 / n
     a = torch.from_numpy(u0).cuda()
     b = torch.empty_like(a)
@@ -446,8 +447,8 @@ def bench_ppm(torch, gd, u0, steps=10, warmup=2):
     stream = torch.cuda.current_stream()
 
     def one(src, dst):
-        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, limiter="ppm", out=dst, want_bflux=False,
-                cfl=0.5, dt_next=dt)
+        gd.step(src, GAMMA, dx, dt_dev=dt, periodic=True, limiter=limiter, out=dst,
+                want_bflux=False, cfl=0.5, dt_next=dt)
 
     gd.cfl_dt(a, GAMMA, dx, 0.5, periodic=True, out=dt)
     for i in range(warmup):
@@ -463,8 +464,9 @@ def bench_ppm(torch, gd, u0, steps=10, warmup=2):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     cells = n ** 3
+    half = "characteristic tracing" if limiter == "ppm_ct" else "Hancock half step"
     return {"workload": f"periodic Euler box {n}^3 FP64 (the turbulent box of the main line), "
-                        "PPM reconstruction (limited parabola) + Hancock half step + HLLC; per step "
+                        f"PPM reconstruction (limited parabola) + {half} + HLLC; per step "
                         "one godunov_step_cfl (predict, update, CFL reduction), dt on the device",
             "ms_per_step": round(ms, 4), "mcell_per_s": cells / (ms * 1e-3) / 1e6,
             "bytes_per_step": 80 * cells, "achieved_gbs": 80 * cells / (ms * 1e-3) / 1e9,
@@ -950,6 +952,7 @@ def main():
         also["amr"] = bench_amr(torch, gd)
     if not args.no_ppm:
         also["ppm"] = bench_ppm(torch, gd, r["u0"])
+        also["ppm_ct"] = bench_ppm(torch, gd, r["u0"], limiter="ppm_ct")
     if not args.no_streamed:
         also["streamed"] = bench_streamed(torch, gd)
     if not args.no_adjoint:

@@ -98,7 +98,9 @@ typedef enum { GD_GHOSTED = 0, GD_PERIODIC = 1 } gd_bc;      /* layout of the in
 typedef enum {
     GD_MINMOD = 0, GD_MC = 1, GD_UNLIMITED = 2,
     GD_PPM = 3,             /* piecewise-parabolic reconstruction (see below) */
-    GD_PPM_UNLIMITED = 4    /* the same parabola without its limiters */
+    GD_PPM_UNLIMITED = 4,   /* the same parabola without its limiters */
+    GD_PPM_CT = 5,          /* GD_PPM with characteristic tracing (see below) */
+    GD_PPM_CT_UNLIMITED = 6 /* GD_PPM_UNLIMITED with characteristic tracing */
 } gd_limiter;
 typedef enum { GD_HLLC = 0, GD_HLL = 1 } gd_riemann;
 
@@ -292,6 +294,22 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
  *   the Hancock half step of step 3 with slopes a_R - a_L, and the face
  *     states W* + (a_R - W) (upper face) and W* + (a_L - W) (lower face),
  *     floored; steps 5-7 unchanged.
+ * GD_PPM_CT and GD_PPM_CT_UNLIMITED replace the last two items by Colella &
+ * Woodward's characteristic tracing along each axis d: with the waves of the
+ * primitive system along d at the cell's state (speeds u_d - c, u_d (entropy
+ * and two shear waves), u_d + c, Courant numbers s = speed dt/dx), the state
+ * on the upper face is a_R + sum over the waves with s > 0 of
+ * (l . (A(s) - a_R)) r, A(s) - a_R = -(s/2)(a_R - a_L - (1 - 2s/3) a_6),
+ * a_6 = 6 (a - (a_L + a_R)/2) -- the parabolas' average over the last s of
+ * the cell minus the edge -- and on the lower face a_L + the same over the
+ * waves with s < 0 with A(s) - a_L = (|s|/2)(a_R - a_L + (1 - 2|s|/3) a_6);
+ * l, r the left and right eigenvectors in (rho, u_n, u_t1, u_t2, p):
+ * r = (1, -+c/rho, 0, 0, c^2), l = (0, -+rho/(2c), 0, 0, 1/(2c^2)) for u -+ c;
+ * entropy r = (1, 0, 0, 0, 0), l = (1, 0, 0, 0, -1/c^2); shear waves the
+ * transverse velocities. Each face state then gains the Hancock terms of the
+ * two other axes, -dt/(2dx) sum_{d' != d} A_d'(W) (a_R,d' - a_L,d'), and is
+ * floored. For a contact this is the PPM advection scheme (third order on
+ * smooth data for the unlimited parabola).
  * A ghosted patch needs ng >= 3 (GD_E_ARG otherwise): the stencil reads face
  * ghosts to depth 3 and edge ghosts at depths (1, <= 2); corners never. The
  * library keeps a device scratch of 30 values per cell of the patch's box

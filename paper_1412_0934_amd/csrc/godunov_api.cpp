@@ -132,7 +132,7 @@ int check_opts(gd_ctx *ctx, const gd_opts *o)
     if (!o) return fail(ctx, GD_E_ARG, "opts is NULL");
     if (o->dtype != GD_F64 && o->dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", o->dtype);
     if (o->bc != GD_GHOSTED && o->bc != GD_PERIODIC) return fail(ctx, GD_E_ARG, "bad bc %d", o->bc);
-    if (o->limiter < GD_MINMOD || o->limiter > GD_PPM_UNLIMITED)
+    if (o->limiter < GD_MINMOD || o->limiter > GD_PPM_CT_UNLIMITED)
         return fail(ctx, GD_E_ARG, "bad limiter %d", o->limiter);
     if (o->riemann != GD_HLLC && o->riemann != GD_HLL)
         return fail(ctx, GD_E_ARG, "bad riemann solver %d", o->riemann);
@@ -143,7 +143,7 @@ int check_opts(gd_ctx *ctx, const gd_opts *o)
 
 size_t elem_size(const gd_opts *o) { return o->dtype == GD_F32 ? 4 : 8; }
 
-bool is_ppm(const gd_opts *o) { return o->limiter == GD_PPM || o->limiter == GD_PPM_UNLIMITED; }
+bool is_ppm(const gd_opts *o) { return o->limiter >= GD_PPM && o->limiter <= GD_PPM_CT_UNLIMITED; }
 
 int reject_ppm(gd_ctx *ctx, const gd_opts *o, const char *what)
 {

@@ -9,6 +9,13 @@
 // local extremum and the overshoot corrections a_L = 3a - 2a_R or
 // a_R = 3a - 2a_L. The Hancock half step uses the slopes a_R - a_L; the face
 // states are W* + (a_R - W) on the upper face and W* + (a_L - W) on the lower.
+// With characteristic tracing (GD_PPM_CT, GD_PPM_CT_UNLIMITED) the face states
+// along each axis come instead from the waves of the primitive system along
+// that axis (speeds u - c, u, u + c): the edge value plus, for each wave moving
+// towards the face, its eigenvector times its projection of (the parabolas'
+// average over the part of the cell the wave sweeps in dt - the edge value)
+// (Colella & Woodward 1984), plus the Hancock step's terms of the two other
+// axes.
 //
 // Two launches per step, over a scratch of 30 values per predicted cell:
 //   ppm_predict  16 x 16 column tiles of the cells whose face states some
@@ -137,6 +144,93 @@ __device__ __forceinline__ void ppm_edges(T amm, T am, T a0, T ap, T app, T &aL,
     aR = r;
 }
 
+// The parabola's average over the last s of the cell minus a_R (upper face,
+// s > 0), or over the first -s of the cell minus a_L (lower face, s < 0).
+template <bool UPPER, typename T>
+__device__ __forceinline__ T ppm_sweep_minus_edge(T aL, T aR, T a0, T s)
+{
+    const T da = aR - aL, a6 = T(6) * (a0 - T(0.5) * (aL + aR));
+    if constexpr (UPPER) return T(-0.5) * s * (da - (T(1) - s * T(2.0 / 3.0)) * a6);
+    else return T(-0.5) * s * (da + (T(1) + s * T(2.0 / 3.0)) * a6);
+}
+
+// The traced state on the upper (UPPER) or lower face along axis D of a cell
+// with primitive state W, parabola edges aL, aR, sound speed c and 1/c, and
+// dt/dx = cfl; eigenvectors in (rho, u_n, u_t1, u_t2, p):
+// r_-+ = (1, -+c/rho, 0, 0, c^2), l_-+ = (0, -+rho/(2c), 0, 0, 1/(2c^2));
+// entropy r = (1, 0, 0, 0, 0), l = (1, 0, 0, 0, -1/c^2); shear: the transverse
+// velocities.
+template <int D, bool UPPER, typename T>
+__device__ __forceinline__ void ppm_trace(const T W[5], const T aL[5], const T aR[5], T c, T inv_c,
+                                          T inv_rho, T cfl, T out[5])
+{
+    constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
+    const T un = W[n];
+    const T s[3] = { (un - c) * cfl, un * cfl, (un + c) * cfl };
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q] = UPPER ? aR[q] : aL[q];
+    const T half_rho_ic = T(0.5) * W[0] * inv_c, half_ic2 = T(0.5) * inv_c * inv_c;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        const bool towards = UPPER ? s[w] > T(0) : s[w] < T(0);
+        if (!towards) continue;
+        const T Dn = ppm_sweep_minus_edge<UPPER>(aL[n], aR[n], W[n], s[w]);
+        const T Dp = ppm_sweep_minus_edge<UPPER>(aL[4], aR[4], W[4], s[w]);
+        if (w == 1) {
+            // entropy and shear waves
+            out[0] += ppm_sweep_minus_edge<UPPER>(aL[0], aR[0], W[0], s[w]) -
+                      T(2) * half_ic2 * Dp;
+            out[t1] += ppm_sweep_minus_edge<UPPER>(aL[t1], aR[t1], W[t1], s[w]);
+            out[t2] += ppm_sweep_minus_edge<UPPER>(aL[t2], aR[t2], W[t2], s[w]);
+        } else {
+            const T sg = w == 0 ? T(-1) : T(1);
+            const T beta = sg * half_rho_ic * Dn + half_ic2 * Dp;
+            out[0] += beta;
+            out[n] += sg * c * inv_rho * beta;
+            out[4] += c * c * beta;
+        }
+    }
+}
+
+// The Hancock half step's terms from the slopes a_R - a_L along axis D alone:
+// W* - W = -dt/(2dx) (C_x + C_y + C_z), C_D = A_D(W) (a_R,D - a_L,D).
+template <int D, typename T>
+__device__ __forceinline__ void hancock_axis_term(const T W[5], T inv_rho, const T aL[5],
+                                                  const T aR[5], T gamma, T C[5])
+{
+    constexpr int n = 1 + D;
+    const T Sn = aR[n] - aL[n], Sp = aR[4] - aL[4];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) C[q] = W[n] * (aR[q] - aL[q]);
+    C[0] += W[0] * Sn;
+    C[n] += Sp * inv_rho;
+    C[4] += gamma * W[4] * Sn;
+}
+
+// The two face states of a cell along axis D by characteristic tracing, each
+// with the Hancock terms of the two other axes (E1, E2), floored.
+template <int D, int E1, int E2, typename T>
+__device__ __forceinline__ void ppm_traced_faces(const T W[5], T inv_rho, const T aL[3][5],
+                                                 const T aR[3][5], T c, T inv_c, T lam,
+                                                 const Phys<T> &ph, T lo[5], T hi[5], int &hits)
+{
+    ppm_trace<D, false>(W, aL[D], aR[D], c, inv_c, inv_rho, T(2) * lam, lo);
+    ppm_trace<D, true>(W, aL[D], aR[D], c, inv_c, inv_rho, T(2) * lam, hi);
+    T C1[5], C2[5];
+    hancock_axis_term<E1>(W, inv_rho, aL[E1], aR[E1], ph.gamma, C1);
+    hancock_axis_term<E2>(W, inv_rho, aL[E2], aR[E2], ph.gamma, C2);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T tr = -lam * (C1[q] + C2[q]);
+        lo[q] += tr;
+        hi[q] += tr;
+    }
+    lo[0] = floored(lo[0], ph.rho_floor, hits);
+    lo[4] = floored(lo[4], ph.p_floor, hits);
+    hi[0] = floored(hi[0], ph.rho_floor, hits);
+    hi[4] = floored(hi[4], ph.p_floor, hits);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_prim(const T *__restrict__ u, const Addr &A, int i, int j, int k,
                                           const Phys<T> &ph, T W[5], T &inv, int &hits)
@@ -174,7 +268,7 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ u, const Addr &A,
     for (int q = 0; q < 5; ++q) U[q] = u[o + q * A.vs];
 }
 
-template <typename T, int MODE, bool BATCHED>
+template <typename T, int MODE, bool CT, bool BATCHED>
 __global__ __launch_bounds__(PT * PT) void ppm_predict_kernel(
     PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmTile *__restrict__ tiles,
     const int64_t *__restrict__ soff, const T *__restrict__ u_base, T *__restrict__ scratch,
@@ -292,25 +386,50 @@ __global__ __launch_bounds__(PT * PT) void ppm_predict_kernel(
 #pragma unroll
                 for (int d = 0; d < 3; ++d) S[d][q] = aR[d][q] - aL[d][q];
             }
-            T Ws[5];
-            predictor(W, winv[2], S[0], S[1], S[2], lam, ph.gamma, Ws);
             T *__restrict__ out = scratch + so + ((int64_t)kb * B.by + bj) * B.bx + bi;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            if constexpr (CT) {
+                const T gp = ph.gamma * W[4];
+                const T r = fast_rsqrt(gp * W[0]);
+                const T c = gp * r, inv_c = W[0] * r;      // sqrt(gamma p / rho) and its inverse
                 T lo[5], hi[5];
+                ppm_traced_faces<0, 1, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
-                    lo[q] = Ws[q] + (aL[d][q] - W[q]);
-                    hi[q] = Ws[q] + (aR[d][q] - W[q]);
+                    out[(int64_t)(0 * 5 + q) * B.n] = lo[q];
+                    out[(int64_t)(1 * 5 + q) * B.n] = hi[q];
                 }
-                hits += (lo[0] < ph.rho_floor) + (lo[4] < ph.p_floor) + (hi[0] < ph.rho_floor) +
-                        (hi[4] < ph.p_floor);
-                lo[0] = fmax(lo[0], ph.rho_floor); lo[4] = fmax(lo[4], ph.p_floor);
-                hi[0] = fmax(hi[0], ph.rho_floor); hi[4] = fmax(hi[4], ph.p_floor);
+                ppm_traced_faces<1, 0, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
-                    out[(int64_t)((2 * d) * 5 + q) * B.n] = lo[q];
-                    out[(int64_t)((2 * d + 1) * 5 + q) * B.n] = hi[q];
+                    out[(int64_t)(2 * 5 + q) * B.n] = lo[q];
+                    out[(int64_t)(3 * 5 + q) * B.n] = hi[q];
+                }
+                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    out[(int64_t)(4 * 5 + q) * B.n] = lo[q];
+                    out[(int64_t)(5 * 5 + q) * B.n] = hi[q];
+                }
+            } else {
+                T Ws[5];
+                predictor(W, winv[2], S[0], S[1], S[2], lam, ph.gamma, Ws);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    T lo[5], hi[5];
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        lo[q] = Ws[q] + (aL[d][q] - W[q]);
+                        hi[q] = Ws[q] + (aR[d][q] - W[q]);
+                    }
+                    lo[0] = floored(lo[0], ph.rho_floor, hits);
+                    lo[4] = floored(lo[4], ph.p_floor, hits);
+                    hi[0] = floored(hi[0], ph.rho_floor, hits);
+                    hi[4] = floored(hi[4], ph.p_floor, hits);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        out[(int64_t)((2 * d) * 5 + q) * B.n] = lo[q];
+                        out[(int64_t)((2 * d + 1) * 5 + q) * B.n] = hi[q];
+                    }
                 }
             }
         }
@@ -414,7 +533,7 @@ __global__ __launch_bounds__(PPM_BLOCK) void ppm_update_kernel(
     }
 }
 
-template <typename T, int MODE, int RS>
+template <typename T, int MODE, bool CT, int RS>
 int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *pitems, int npitems,
                  const PpmItem *uitems, int nuitems, const int64_t *soff, const void *u_in,
                  void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
@@ -422,7 +541,7 @@ int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *p
 {
     if (patches) {
         if (npitems == 0 || nuitems == 0) return 0;
-        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, true>), dim3(npitems), dim3(PT * PT), 0, s,
+        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, CT, true>), dim3(npitems), dim3(PT * PT), 0, s,
                            P1, patches, pitems, soff, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
         hipLaunchKernelGGL((ppm_update_kernel<T, RS, true>), dim3(nuitems), dim3(PPM_BLOCK), 0, s,
                            P1, patches, uitems, soff, (const T *)u_in, (const T *)scratch, (T *)u_out,
@@ -435,7 +554,7 @@ int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *p
     const int64_t ntiles = (int64_t)((P1.nx + 2 * e + PT - 1) / PT) * ((P1.ny + 2 * e + PT - 1) / PT) *
                            ((P1.nz + 2 * e + PZ - 1) / PZ);
     (void)nbox;
-    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, false>), dim3((unsigned)ntiles), dim3(PT * PT), 0, s, P1,
+    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, CT, false>), dim3((unsigned)ntiles), dim3(PT * PT), 0, s, P1,
                        nullptr, nullptr, nullptr, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
     hipLaunchKernelGGL((ppm_update_kernel<T, RS, false>),
                        dim3((unsigned)((ncell + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
@@ -450,15 +569,27 @@ int launch_ppm_d(int limiter, int riemann, const PatchDesc &P1, const PatchDesc 
                  const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
                  const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
 {
-#define GD_PPM(M, R) return launch_ppm_t<T, M, R>(P1, patches, pitems, npitems, uitems, nuitems, soff, \
-                                                  u_in, u_out, bflux, scratch, dt_dev, sc, hits, s)
-    const bool central = limiter == 4;
+#define GD_PPM(M, C, R) return launch_ppm_t<T, M, C, R>(P1, patches, pitems, npitems, uitems, nuitems, \
+                                                        soff, u_in, u_out, bflux, scratch, dt_dev, sc, \
+                                                        hits, s)
+    // limiters 3, 4: Hancock half step with the limited / unlimited parabola;
+    // 5, 6: characteristic tracing with the limited / unlimited parabola
+    const bool central = limiter == 4 || limiter == 6;
+    const bool traced = limiter == 5 || limiter == 6;
     if (riemann == RS_HLL) {
-        if (central) GD_PPM(PPM_CENTRAL, RS_HLL);
-        GD_PPM(PPM_LIMITED, RS_HLL);
+        if (traced) {
+            if (central) GD_PPM(PPM_CENTRAL, true, RS_HLL);
+            GD_PPM(PPM_LIMITED, true, RS_HLL);
+        }
+        if (central) GD_PPM(PPM_CENTRAL, false, RS_HLL);
+        GD_PPM(PPM_LIMITED, false, RS_HLL);
     }
-    if (central) GD_PPM(PPM_CENTRAL, RS_HLLC);
-    GD_PPM(PPM_LIMITED, RS_HLLC);
+    if (traced) {
+        if (central) GD_PPM(PPM_CENTRAL, true, RS_HLLC);
+        GD_PPM(PPM_LIMITED, true, RS_HLLC);
+    }
+    if (central) GD_PPM(PPM_CENTRAL, false, RS_HLLC);
+    GD_PPM(PPM_LIMITED, false, RS_HLLC);
 #undef GD_PPM
 }
 

@@ -36,7 +36,8 @@ LIB_PATH = os.environ.get("GODUNOV_LIB", os.path.join(_HERE, "libgodunov.so"))
 
 GD_OK, GD_E_ARG, GD_E_HIP, GD_E_NOMEM, GD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 DTYPES = {torch.float64: 0, torch.float32: 1}
-LIMITERS = {"minmod": 0, "mc": 1, "unlimited": 2, "none": 2, "ppm": 3, "ppm_unlimited": 4}
+LIMITERS = {"minmod": 0, "mc": 1, "unlimited": 2, "none": 2, "ppm": 3, "ppm_unlimited": 4,
+            "ppm_ct": 5, "ppm_ct_unlimited": 6}
 RIEMANN = {"hllc": 0, "hll": 1}
 RHO_FLOOR = 1e-10
 P_FLOOR = 1e-10
