@@ -21,7 +21,28 @@ template <int TX, int TY>
 struct TileGeom {
     static constexpr int NINT = TX * TY;
     static constexpr int NT = tile_threads(TX, TY);
+    // faces of a plane: the x faces i-1/2 (i = 0..TX) of each row, then the y
+    // faces j-1/2 (j = 0..TY) of each column
+    static constexpr int NXF = TY * (TX + 1);
+    static constexpr int NF = NXF + (TY + 1) * TX;
+    static constexpr int NSLOT = (NF + NT - 1) / NT;    // faces per thread
+    __device__ static constexpr int xface(int i, int j) { return j * (TX + 1) + i; }
+    __device__ static constexpr int yface(int i, int j) { return NXF + j * TX + i; }
+    // (i, j) of face t; true for an x face
+    __device__ static bool face_ij(int t, int &i, int &j)
+    {
+        const bool isx = t < NXF;
+        const int u = isx ? t : t - NXF;
+        i = isx ? u % (TX + 1) : u % TX;
+        j = isx ? u / (TX + 1) : u / TX;
+        return isx;
+    }
 };
+
+// Storage slot of primitive component q in a y-face state: y faces are kept in
+// their rotated order (rho, v, w, u, p), x faces in the natural one, so a face
+// reads and writes slots 0..4 whatever its orientation.
+__device__ constexpr int yslot(int q) { return q == 1 ? 3 : (q == 2 ? 1 : (q == 3 ? 2 : q)); }
 
 // ------------------------------------------------------------ addressing
 
@@ -120,14 +141,12 @@ struct TileSmem {
     // primitives of plane k with its two-deep x-y halo (the column's own
     // planes k-1 and k+1 live in registers)
     T w[5][TY + 4][TX + 4];
-    // face states of the plane: x face i-1/2 of row j has its left state in
-    // xl[.][j][i] and its right state in xr[.][j][i]; likewise y face j-1/2 of
-    // column i in yl/yr[.][j][i]. The flux through a face overwrites its left
-    // state (the thread that evaluates a face is the only one touching it).
-    T xl[5][TY][TX + 1];
-    T xr[5][TY][TX + 1];
-    T yl[5][TY + 1][TX];
-    T yr[5][TY + 1][TX];
+    // face states of the plane, indexed as TileGeom::xface / yface, left
+    // (lower) state in fl and right (upper) state in fr, y faces in rotated
+    // slots (yslot). The flux through a face overwrites its left state (the
+    // thread that evaluates a face is the only one touching it).
+    T fl[5][TileGeom<TX, TY>::NF];
+    T fr[5][TileGeom<TX, TY>::NF];
 };
 
 enum { ROLE_NONE = -1, ROLE_INT = 0, ROLE_BOTTOM = 1, ROLE_TOP = 2, ROLE_LEFT = 3, ROLE_RIGHT = 4 };
@@ -151,8 +170,7 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                              TileSmem<T, TX, TY> &sm, int &hits, bool want_cfl, double &smax)
 {
     using Geo = TileGeom<TX, TY>;
-    constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX;
-    constexpr int XVS = TY * (TX + 1), YVS = (TY + 1) * TX;    // LDS variable strides
+    constexpr int NF = Geo::NF;
     const int tid = threadIdx.x;
     const int ax = min(TX, P.nx - x0);
     const int ay = min(TY, P.ny - y0);
@@ -237,6 +255,17 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
     }
     if (halo) load5(uin + view.plane(z0) + hcol, view.vstride, Hpf);
 
+    // the faces this thread evaluates in phase C1, and whether each lies in
+    // the clipped tile
+    unsigned fact = 0;
+#pragma unroll
+    for (int s = 0; s < Geo::NSLOT; ++s) {
+        const int t = tid + s * Geo::NT;
+        int i, j;
+        const bool isx = Geo::face_ij(t, i, j);
+        if (t < NF && (isx ? (i <= ax && j < ay) : (i < ax && j <= ay))) fact |= 1u << s;
+    }
+
     const int lx = ci + 2, ly = cj + 2;
     const T half = T(0.5);
     for (int k = z0 - 1; k <= z1; ++k) {
@@ -285,76 +314,79 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
                 face_state(Ws, Sz, half, zprev, ph, hits);
             } else if (post) {
                 face_state(Ws, Sz, -half, zm, ph, hits);
-            } else {
+            } else if (interior) {
                 T st[5];
-                if (interior || role == ROLE_LEFT) {
-                    face_state(Ws, Sx, half, st, ph, hits);
+                face_state(Ws, Sx, half, st, ph, hits);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) sm.xl[q][cj][ci + 1] = st[q];
-                }
-                if (interior || role == ROLE_RIGHT) {
-                    face_state(Ws, Sx, -half, st, ph, hits);
+                for (int q = 0; q < 5; ++q) sm.fl[q][Geo::xface(ci + 1, cj)] = st[q];
+                face_state(Ws, Sx, -half, st, ph, hits);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) sm.xr[q][cj][ci] = st[q];
-                }
-                if (interior || role == ROLE_BOTTOM) {
-                    face_state(Ws, Sy, half, st, ph, hits);
+                for (int q = 0; q < 5; ++q) sm.fr[q][Geo::xface(ci, cj)] = st[q];
+                face_state(Ws, Sy, half, st, ph, hits);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) sm.yl[q][cj + 1][ci] = st[q];
-                }
-                if (interior || role == ROLE_TOP) {
-                    face_state(Ws, Sy, -half, st, ph, hits);
+                for (int q = 0; q < 5; ++q) sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] = st[q];
+                face_state(Ws, Sy, -half, st, ph, hits);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) sm.yr[q][cj][ci] = st[q];
-                }
-                if (interior) {
-                    face_state(Ws, Sz, -half, zm, ph, hits);
-                    face_state(Ws, Sz, half, zpn, ph, hits);
-                }
+                for (int q = 0; q < 5; ++q) sm.fr[yslot(q)][Geo::yface(ci, cj)] = st[q];
+                face_state(Ws, Sz, -half, zm, ph, hits);
+                face_state(Ws, Sz, half, zpn, ph, hits);
+            } else {
+                // a ring column: the one state its face with the tile needs,
+                // direction and side selected per lane, so that a wave holding
+                // ring columns of all four sides evaluates a single face state.
+                // The face is an x face for the left and right columns, a y
+                // face for the bottom and top rows; the left and bottom
+                // columns hold the face's left (lower) state.
+                const bool ring_x = role == ROLE_LEFT || role == ROLE_RIGHT;
+                const bool ring_lo = role == ROLE_LEFT || role == ROLE_BOTTOM;
+                const int ring_face =
+                    ring_x ? Geo::xface(ci + ring_lo, cj) : Geo::yface(ci, cj + ring_lo);
+                T S[5], st[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) S[q] = ring_x ? Sx[q] : Sy[q];
+                face_state(Ws, S, ring_lo ? half : -half, st, ph, hits);
+                T *dst = ring_lo ? &sm.fl[0][ring_face] : &sm.fr[0][ring_face];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) dst[(ring_x ? q : yslot(q)) * NF] = st[q];
             }
         }
         if (!post) __syncthreads();
         if (pre) continue;
 
-        // ---- C1: x and y faces as tasks over all threads. Task t < NXF is
-        // x face (i, j) = (t % (TX+1), t / (TX+1)); the rest are y faces
-        // (i, j) = (u % TX, u / TX) with u = t - NXF. States are read and
-        // fluxes written through per-lane LDS addresses in rotated order
-        // (normal velocity first), so one code path serves both directions.
+        // ---- C1: the x and y faces of the plane, NSLOT per thread (face t =
+        // tid + s NT). Both orientations read their states from and write their
+        // flux to slots 0..4 of face t, so the task needs no per-face address
+        // arithmetic; only the boundary-flux sheets need the face's (i, j).
         if (!post) {
-            for (int t = tid; t < NXF + NYF; t += Geo::NT) {
-                const bool isx = t < NXF;
-                const int u = isx ? t : t - NXF;
-                const int i = isx ? u % (TX + 1) : u % TX;
-                const int j = isx ? u / (TX + 1) : u / TX;
-                const bool active = isx ? (i <= ax && j < ay) : (i < ax && j <= ay);
-                if (!active) continue;
-                T *lb = isx ? &sm.xl[0][j][i] : &sm.yl[0][j][i];
-                const T *rb = isx ? &sm.xr[0][j][i] : &sm.yr[0][j][i];
-                const int vs = isx ? XVS : YVS;
-                // rotated component offsets: x (u, v, w), y (v, w, u)
-                const int on = (isx ? 1 : 2) * vs, o1 = (isx ? 2 : 3) * vs, o2 = (isx ? 3 : 1) * vs;
-                T L[5] = { lb[0], lb[on], lb[o1], lb[o2], lb[4 * vs] };
-                T R[5] = { rb[0], rb[on], rb[o1], rb[o2], rb[4 * vs] };
-                T G[5];
+            // not unrolled: two faces in flight at once would double the
+            // registers the Riemann solver holds
+#pragma unroll 1
+            for (int s = 0; s < Geo::NSLOT; ++s) {
+                if (!((fact >> s) & 1u)) continue;
+                const int t = tid + s * Geo::NT;
+                T L[5], R[5], G[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    L[q] = sm.fl[q][t];
+                    R[q] = sm.fr[q][t];
+                }
                 riemann<RS>(L, R, ph, G);
-                lb[0] = G[0]; lb[on] = G[1]; lb[o1] = G[2]; lb[o2] = G[3]; lb[4 * vs] = G[4];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fl[q][t] = G[q];
                 if (want_flux) {
+                    int i, j;
+                    const bool isx = Geo::face_ij(t, i, j);
                     const int fi = x0 + i, fj = y0 + j;
-                    T F[5];
-                    F[0] = G[0]; F[4] = G[4];
-                    F[1] = isx ? G[1] : G[3];
-                    F[2] = isx ? G[2] : G[1];
-                    F[3] = isx ? G[3] : G[2];
                     if (isx && (fi == 0 || fi == P.nx)) {
                         T *sheet = bf + (fi == 0 ? 0 : 5 * sxs);
 #pragma unroll
-                        for (int q = 0; q < 5; ++q) sheet[q * sxs + (int64_t)k * P.ny + fj] = F[q];
+                        for (int q = 0; q < 5; ++q) sheet[q * sxs + (int64_t)k * P.ny + fj] = G[q];
                     }
                     if (!isx && (fj == 0 || fj == P.ny)) {
                         T *sheet = bf + 10 * sxs + (fj == 0 ? 0 : 5 * sys);
 #pragma unroll
-                        for (int q = 0; q < 5; ++q) sheet[q * sys + (int64_t)k * P.nx + fi] = F[q];
+                        for (int q = 0; q < 5; ++q)
+                            sheet[q * sys + (int64_t)k * P.nx + fi] = G[yslot(q)];
                     }
                 }
             }
@@ -400,8 +432,9 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
         if (interior) {
 #pragma unroll
             for (int q = 0; q < 5; ++q)
-                acc[q] = ((sm.xl[q][cj][ci + 1] - sm.xl[q][cj][ci]) +
-                          (sm.yl[q][cj + 1][ci] - sm.yl[q][cj][ci])) + acc[q];
+                acc[q] = ((sm.fl[q][Geo::xface(ci + 1, cj)] - sm.fl[q][Geo::xface(ci, cj)]) +
+                          (sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] -
+                           sm.fl[yslot(q)][Geo::yface(ci, cj)])) + acc[q];
         }
     }
 }
