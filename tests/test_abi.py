@@ -198,16 +198,18 @@ def test_amr_calls_reject_a_null_plan(lib):
 
 
 def test_ppm_options_are_checked(lib):
-    """limiter 3 and 4 select the PPM reconstruction: a ghosted patch needs
-    three ghost layers, limiter 5 does not exist, and the adjoint, the MHD
-    step and the autotuner refuse PPM (GD_E_UNSUPPORTED) before anything else."""
-    assert _step(lib, _opts(limiter=3), ng=2) == -1
-    assert b"ng >= 3" in lib.gd_last_error(None)
-    assert _step(lib, _opts(limiter=4), ng=3) == -1          # valid: stops at the NULL ctx
-    assert b"ctx" in lib.gd_last_error(None)
-    assert _step(lib, _opts(limiter=5), ng=3) == -1
+    """limiters 3 to 6 select the PPM reconstructions (with and without
+    characteristic tracing): a ghosted patch needs three ghost layers, limiter
+    7 does not exist, and the adjoint and the MHD step refuse PPM
+    (GD_E_UNSUPPORTED) before anything else."""
+    for lim in (3, 4, 5, 6):
+        assert _step(lib, _opts(limiter=lim), ng=2) == -1
+        assert b"ng >= 3" in lib.gd_last_error(None)
+        assert _step(lib, _opts(limiter=lim), ng=3) == -1    # valid: stops at the NULL ctx
+        assert b"ctx" in lib.gd_last_error(None)
+    assert _step(lib, _opts(limiter=7), ng=3) == -1
     assert b"limiter" in lib.gd_last_error(None)
-    o = _opts(limiter=3, bc=1)
+    o = _opts(limiter=5, bc=1)
     r = lib.godunov_step_adjoint(None, ctypes.byref(o), 4, 4, 4, 0, ctypes.c_void_p(16),
                                  ctypes.c_void_p(1 << 20), None, ctypes.c_void_p(1 << 24),
                                  5 / 3, 0.1, 0.01, None)
