@@ -609,6 +609,17 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
     hipStream_t s = (hipStream_t)hip_stream;
     const Slot slot = slot_for(ctx, s);
+    if (is_ppm(opts) && (!periodic || std::min(nx, std::min(ny, nz)) >= 2)) {
+        // the PPM step of one patch: one fused launch, no scratch (its
+        // stencils reach three cells past a tile, which two wraps of a
+        // periodic coordinate cover only for extents of 2 and more)
+        gd::CflOut co{ cfl, dt_next, slot.u64 + 2, slot.u32 + 3 };
+        int e = gd::launch_ppm_tile(opts->dtype, opts->limiter, opts->riemann, P, u_in, u_out, bflux,
+                                    dt_dev, sc, ctx->d_u64, 2 * ctx->num_cus, co, s);
+        if (!e && dt_next) e = gd::launch_cfl_finalize(cfl, dt_next, co.smax_bits, s);
+        if (e) return hip_fail(ctx, e, "PPM step launch");
+        return GD_OK;
+    }
     if (is_ppm(opts)) {
         if ((r = ensure_ppm_scratch(ctx, (size_t)gd::ppm_box_cells(P) * 30 * es, s))) return r;
         int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, P, nullptr, nullptr, 0,

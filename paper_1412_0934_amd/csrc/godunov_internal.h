@@ -205,4 +205,15 @@ int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const P
                const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
                const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s);
 
+// One PPM step (limiters 3 to 6) of a single patch in one launch: the tile
+// march of the PLM step with the parabola, no face-state scratch; with
+// co.dt_next the CFL signal of the new state is reduced into co.smax_bits
+// (launch_cfl_finalize turns it into dt).
+constexpr int PPM_FUSED_TX = 24, PPM_FUSED_TY = 8;
+int launch_ppm_tile(int dtype, int limiter, int riemann, const PatchDesc &P, const void *u_in,
+                    void *u_out, void *bflux, const double *dt_dev, const Scalars &sc,
+                    unsigned long long *hits, int min_blocks, const CflOut &co, hipStream_t s);
+// dt = cfl / (the maximum folded into smax_bits), which is cleared for the next use
+int launch_cfl_finalize(double cfl, double *dt_out, unsigned long long *smax_bits, hipStream_t s);
+
 }  // namespace gd

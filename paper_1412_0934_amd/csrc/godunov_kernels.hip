@@ -347,6 +347,12 @@ static int occupancy_t(int shape, int device)
     return n;
 }
 
+int launch_cfl_finalize(double cfl, double *dt_out, unsigned long long *smax_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, cfl, dt_out, smax_bits);
+    return (int)hipGetLastError();
+}
+
 int max_resident_blocks(int dtype, int limiter, int riemann, int shape, int device)
 {
     if (dtype == 1) GD_DISPATCH_SCHEME(occupancy_t, float, shape, device);

@@ -17,7 +17,10 @@
 // (Colella & Woodward 1984), plus the Hancock step's terms of the two other
 // axes.
 //
-// Two launches per step, over a scratch of 30 values per predicted cell:
+// A single patch takes one launch per step (ppm_tile_kernel, the tile march
+// of the PLM step with the parabola: the face states stay in LDS and
+// registers). Batches, and periodic boxes thinner than two cells, take two
+// launches per step over a scratch of 30 values per predicted cell:
 //   ppm_predict  16 x 16 column tiles of the cells whose face states some
 //                face needs (the interior and, for a ghosted patch, the face
 //                ghosts of depth 1), marching in z: each plane converted to
@@ -32,9 +35,12 @@
 // takes a tile, or a 256-cell piece, of one patch from a host-built table).
 #include "godunov_cell.h"
 #include "godunov_internal.h"
+#include "godunov_tile.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 namespace gd {
 
@@ -535,6 +541,445 @@ __global__ __launch_bounds__(PPM_BLOCK) void ppm_update_kernel(
     }
 }
 
+
+// ------------------------------------------------------------ fused PPM tile
+
+// One launch per step for a single patch with the Hancock PPM reconstruction
+// (GD_PPM, GD_PPM_UNLIMITED): the tile march of the PLM step kernel
+// (godunov_tile) with the parabola in place of the limited slope, so that the
+// face states never leave the chip. A workgroup owns a TX x TY column tile and
+// a z-range; interior and ring columns keep planes k-2 .. k+2 of their column
+// in registers, and each plane of the tile is staged in LDS with the cells of
+// the five-point x and y stencils of its interior and ring cells (a halo three
+// deep along the axes, 4TX + 4TY + 12 cells). Per plane k:
+//   A  columns convert plane k+2 (loaded a plane earlier) and stage plane k;
+//      halo threads stage their cell of plane k;
+//   B  interior and ring columns: the parabola edges of the 15 primitives
+//      (x and y stencils from LDS, z from registers), the Hancock predictor,
+//      and the face states W* + (a_L - W) below and W* + (a_R - W) above,
+//      floored; x and y states to LDS (a ring column only the state its face
+//      with the tile needs), z states in registers;
+//   C  the plane's x and y faces as in the PLM tile, then the z face below
+//      the plane, which completes plane k-1 (and its CFL signal);
+//   D  the x-y flux divergence of plane k.
+// The pre plane z0-1 only produces the state below face z0-1/2's right side,
+// the post plane z1 only the state that completes plane z1-1.
+template <typename T, int TX, int TY>
+struct PpmTileSmem {
+    T w[5][TY + 6][TX + 6];                    // plane k, offset 3
+    T fl[5][TileGeom<TX, TY>::NF];
+    T fr[5][TileGeom<TX, TY>::NF];
+};
+
+template <int TX, int TY>
+constexpr int ppm_halo_cells() { return 4 * TX + 4 * TY + 12; }
+
+template <typename T, int MODE, bool CT, int RS, int TX, int TY, bool GHOSTED>
+__device__ void ppm_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
+                         T *__restrict__ u_out_base, T *__restrict__ bflux_base, T dtdx, T lam,
+                         const Phys<T> &ph, int x0, int y0, int z0, int z1,
+                         PpmTileSmem<T, TX, TY> &sm, int &hits, bool want_cfl, double &smax)
+{
+    using Geo = TileGeom<TX, TY>;
+    constexpr int NF = Geo::NF, NSLOT = Geo::NSLOT;
+    static_assert(ppm_halo_cells<TX, TY>() <= Geo::NT, "one halo cell per thread at most");
+    const int tid = threadIdx.x;
+    const int ax = min(TX, P.nx - x0);
+    const int ay = min(TY, P.ny - y0);
+    const InputView view = make_view(P);
+    const T *__restrict__ uin = u_in_base + P.in_off;
+
+    // ---- role: an interior column, a ring column, or none
+    int ci = 0, cj = 0, role = ROLE_NONE;
+    if (tid < Geo::NINT) {
+        ci = tid % TX;
+        cj = tid / TX;
+        if (ci < ax && cj < ay) role = ROLE_INT;
+    } else {
+        const int r = tid - Geo::NINT;
+        if (r < ax) { ci = r; cj = -1; role = ROLE_BOTTOM; }
+        else if (r < 2 * ax) { ci = r - ax; cj = ay; role = ROLE_TOP; }
+        else if (r < 2 * ax + ay) { ci = -1; cj = r - 2 * ax; role = ROLE_LEFT; }
+        else if (r < 2 * ax + 2 * ay) { ci = ax; cj = r - 2 * ax - ay; role = ROLE_RIGHT; }
+    }
+    const bool owner = role != ROLE_NONE;
+    const bool interior = role == ROLE_INT;
+    const int gi = x0 + ci, gj = y0 + cj;
+    const int64_t col = view.column(gi, gj);
+
+    // ---- the halo cell of this thread: the cells two deep beside the
+    // interior rows and columns, then those three deep, then the twelve cells
+    // around the ring's ends. In the pre and post planes only the interior's
+    // stencils are evaluated, which reach the first group only; in a ghosted
+    // patch the others are neither read nor staged there (so its corner
+    // ghosts, and its edge ghosts three deep, are never read).
+    int hi = 0, hj = 0;
+    const int nhalo = 4 * ax + 4 * ay + 12;
+    const bool halo = tid < nhalo;
+    if (halo) {
+        const int h = tid;
+        if (h < 4 * ay + 4 * ax) {
+            const int deep = h >= 2 * ay + 2 * ax;               // three deep
+            const int g = h - (deep ? 2 * ay + 2 * ax : 0);
+            const int far = g & 1;                               // right or top side
+            if (g < 2 * ay) {
+                hj = g >> 1;
+                hi = far ? ax + 1 + deep : -2 - deep;
+            } else {
+                hi = (g - 2 * ay) >> 1;
+                hj = far ? ay + 1 + deep : -2 - deep;
+            }
+        } else {
+            const int c = h - 4 * ay - 4 * ax;          // 0 .. 11
+            if (c < 8) {
+                // rows -1 and ay: x = -2, -1, ax, ax+1
+                const int w = c & 3;
+                hj = c < 4 ? -1 : ay;
+                hi = w < 2 ? w - 2 : ax + w - 2;
+            } else {
+                // columns -1 and ax, rows -2 and ay+1
+                const int w = c - 8;
+                hi = (w & 1) ? ax : -1;
+                hj = (w & 2) ? ay + 1 : -2;
+            }
+        }
+    }
+    const int64_t hcol = view.column(x0 + hi, y0 + hj);
+
+    // the faces this thread evaluates in phase C1, and whether each lies in
+    // the clipped tile
+    unsigned fact = 0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int t = tid + s * Geo::NT;
+        int i, j;
+        const bool isx = Geo::face_ij(t, i, j);
+        if (t < NF && (isx ? (i <= ax && j < ay) : (i < ax && j <= ay))) fact |= 1u << s;
+    }
+
+    const bool want_flux = bflux_base != nullptr && P.flux_off >= 0;
+    T *__restrict__ bf = want_flux ? bflux_base + P.flux_off : nullptr;
+    const int64_t sxs = (int64_t)P.nz * P.ny, sys = (int64_t)P.nz * P.nx, szs = (int64_t)P.ny * P.nx;
+    T *__restrict__ out = u_out_base + P.out_off;
+    const int64_t ostride = (int64_t)P.nx * P.ny * P.nz;
+    const double inv_dx = 1.0 / P.dx;
+    const int64_t ocol = (int64_t)gj * P.nx + gi;
+
+    // ---- registers: the column's planes k-2 .. k+2, face-state carries
+    T win[5][5], winv[5], Upf[5], Hpf[5], Uold[5];
+    T zprev[5], acc[5], zm[5], zpn[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        winv[q] = T(1);
+        Upf[q] = Hpf[q] = Uold[q] = zprev[q] = acc[q] = zm[q] = zpn[q] = T(0);
+#pragma unroll
+        for (int p = 0; p < 5; ++p) win[p][q] = T(0);
+    }
+    // Every column stages its cell of planes z0-1 .. z1 (the interior's x and
+    // y stencils of the pre and post planes reach the ring), so every
+    // column's window starts at plane z0-3; the last plane an interior column
+    // reads is z1+2, a ring column z1+1 (it computes planes z0 .. z1-1).
+    const int last_plane = interior ? z1 + 2 : z1 + 1;
+    if (owner) {
+        // planes z0-3 .. z0, and the load of plane z0+1, which the first
+        // step converts into the window's top plane
+        // (a ring column never uses plane z0-3: it computes from plane z0)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            if (GHOSTED && p == 0 && !interior) continue;
+            T U[5];
+            load5(uin + view.plane(z0 - 3 + p) + col, view.vstride, U);
+            prim_from_cons(U, win[p], winv[p], ph, hits);
+        }
+        load5(uin + view.plane(z0 + 1) + col, view.vstride, Upf);
+    }
+    if (GHOSTED ? tid < 2 * (ax + ay) : halo) load5(uin + view.plane(z0 - 1) + hcol, view.vstride, Hpf);
+
+    const int lx = ci + 3, ly = cj + 3;
+    for (int k = z0 - 1; k <= z1; ++k) {
+        const bool pre = k < z0;
+        const bool post = k == z1;
+        // a ring column computes planes z0 .. z1-1 only
+        const bool active = interior || (owner && !pre && !post);
+
+        // ---- A: the column's plane k+2, stage plane k. Every thread has
+        // finished reading the previous plane from LDS (phase B, then a
+        // barrier) before it is overwritten here.
+        if (owner) {
+            if (k + 2 <= last_plane) prim_from_cons(Upf, win[4], winv[4], ph, hits);
+            if (k + 3 <= last_plane) load5(uin + view.plane(k + 3) + col, view.vstride, Upf);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.w[q][ly][lx] = win[2][q];
+        }
+        if (GHOSTED && (pre || post) ? tid < 2 * (ax + ay) : halo) {
+            T Wh[5], invh;
+            prim_from_cons(Hpf, Wh, invh, ph, hits);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.w[q][hj + 3][hi + 3] = Wh[q];
+        }
+        if (k + 1 < z1 || !GHOSTED ? (halo && k + 1 <= z1) : (k + 1 == z1 && tid < 2 * (ax + ay)))
+            load5(uin + view.plane(k + 1) + hcol, view.vstride, Hpf);
+        __syncthreads();
+
+        // ---- B: parabola edges, predictor, face states
+        if (active && CT) {
+            // characteristic tracing: per axis both traced face states
+            const T *W = win[2];
+            T aL[3][5], aR[3][5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                ppm_edges<MODE>(sm.w[q][ly][lx - 2], sm.w[q][ly][lx - 1], W[q], sm.w[q][ly][lx + 1],
+                                sm.w[q][ly][lx + 2], aL[0][q], aR[0][q]);
+                ppm_edges<MODE>(sm.w[q][ly - 2][lx], sm.w[q][ly - 1][lx], W[q], sm.w[q][ly + 1][lx],
+                                sm.w[q][ly + 2][lx], aL[1][q], aR[1][q]);
+                ppm_edges<MODE>(win[0][q], win[1][q], W[q], win[3][q], win[4][q], aL[2][q], aR[2][q]);
+            }
+            const T gp = ph.gamma * W[4];
+            const T r = fast_rsqrt(gp * W[0]);
+            const T c = gp * r, inv_c = W[0] * r;      // sqrt(gamma p / rho) and its inverse
+            T lo[5], hi[5];
+            if (pre) {
+                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) zprev[q] = hi[q];
+            } else if (post) {
+                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) zm[q] = lo[q];
+            } else if (interior) {
+                ppm_traced_faces<0, 1, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    sm.fl[q][Geo::xface(ci + 1, cj)] = hi[q];
+                    sm.fr[q][Geo::xface(ci, cj)] = lo[q];
+                }
+                ppm_traced_faces<1, 0, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] = hi[q];
+                    sm.fr[yslot(q)][Geo::yface(ci, cj)] = lo[q];
+                }
+                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, zm, zpn, hits);
+            } else {
+                // a ring column: the traced states of its axis, the one on the
+                // tile side stored (left and bottom columns: the upper state)
+                const bool ring_x = role == ROLE_LEFT || role == ROLE_RIGHT;
+                const bool ring_lo = role == ROLE_LEFT || role == ROLE_BOTTOM;
+                const int ring_face =
+                    ring_x ? Geo::xface(ci + ring_lo, cj) : Geo::yface(ci, cj + ring_lo);
+                if (ring_x) ppm_traced_faces<0, 1, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+                else ppm_traced_faces<1, 0, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+                T *dst = ring_lo ? &sm.fl[0][ring_face] : &sm.fr[0][ring_face];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) dst[(ring_x ? q : yslot(q)) * NF] = ring_lo ? hi[q] : lo[q];
+            }
+        } else if (active) {
+            const T *W = win[2];
+            T aL[3][5], aR[3][5], S[3][5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                ppm_edges<MODE>(sm.w[q][ly][lx - 2], sm.w[q][ly][lx - 1], W[q], sm.w[q][ly][lx + 1],
+                                sm.w[q][ly][lx + 2], aL[0][q], aR[0][q]);
+                ppm_edges<MODE>(sm.w[q][ly - 2][lx], sm.w[q][ly - 1][lx], W[q], sm.w[q][ly + 1][lx],
+                                sm.w[q][ly + 2][lx], aL[1][q], aR[1][q]);
+                ppm_edges<MODE>(win[0][q], win[1][q], W[q], win[3][q], win[4][q], aL[2][q], aR[2][q]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) S[d][q] = aR[d][q] - aL[d][q];
+            }
+            T Ws[5];
+            predictor(W, winv[2], S[0], S[1], S[2], lam, ph.gamma, Ws);
+            // the face state of axis d on the lower (a_L) or upper (a_R) side
+            auto state = [&](const T a[5], T st[5]) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) st[q] = Ws[q] + (a[q] - W[q]);
+                st[0] = floored(st[0], ph.rho_floor, hits);
+                st[4] = floored(st[4], ph.p_floor, hits);
+            };
+            if (pre) {
+                state(aR[2], zprev);
+            } else if (post) {
+                state(aL[2], zm);
+            } else if (interior) {
+                T st[5];
+                state(aR[0], st);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fl[q][Geo::xface(ci + 1, cj)] = st[q];
+                state(aL[0], st);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fr[q][Geo::xface(ci, cj)] = st[q];
+                state(aR[1], st);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] = st[q];
+                state(aL[1], st);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fr[yslot(q)][Geo::yface(ci, cj)] = st[q];
+                state(aL[2], zm);
+                state(aR[2], zpn);
+            } else {
+                // a ring column: the state on the tile side of its face with
+                // the tile; left and bottom columns hold the face's left state
+                const bool ring_x = role == ROLE_LEFT || role == ROLE_RIGHT;
+                const bool ring_lo = role == ROLE_LEFT || role == ROLE_BOTTOM;
+                const int ring_face =
+                    ring_x ? Geo::xface(ci + ring_lo, cj) : Geo::yface(ci, cj + ring_lo);
+                T a[5], st[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    a[q] = ring_x ? (ring_lo ? aR[0][q] : aL[0][q]) : (ring_lo ? aR[1][q] : aL[1][q]);
+                state(a, st);
+                T *dst = ring_lo ? &sm.fl[0][ring_face] : &sm.fr[0][ring_face];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) dst[(ring_x ? q : yslot(q)) * NF] = st[q];
+            }
+        }
+        if (!post) __syncthreads();
+        // the window moves up one plane
+        if (owner) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                winv[p] = winv[p + 1];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) win[p][q] = win[p + 1][q];
+            }
+        }
+        if (pre) continue;
+
+        // ---- C1: the x and y faces of the plane (as in the PLM tile)
+        if (!post) {
+#pragma unroll 1
+            for (int s = 0; s < NSLOT; ++s) {
+                if (!((fact >> s) & 1u)) continue;
+                const int t = tid + s * Geo::NT;
+                T L[5], R[5], G[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    L[q] = sm.fl[q][t];
+                    R[q] = sm.fr[q][t];
+                }
+                riemann<RS>(L, R, ph, G);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sm.fl[q][t] = G[q];
+                if (want_flux) {
+                    int i, j;
+                    const bool isx = Geo::face_ij(t, i, j);
+                    const int fi = x0 + i, fj = y0 + j;
+                    if (isx && (fi == 0 || fi == P.nx)) {
+                        T *sheet = bf + (fi == 0 ? 0 : 5 * sxs);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) sheet[q * sxs + (int64_t)k * P.ny + fj] = G[q];
+                    }
+                    if (!isx && (fj == 0 || fj == P.ny)) {
+                        T *sheet = bf + 10 * sxs + (fj == 0 ? 0 : 5 * sys);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q)
+                            sheet[q * sys + (int64_t)k * P.nx + fi] = G[yslot(q)];
+                    }
+                }
+            }
+        }
+
+        // ---- C2: the z face below the plane; completes plane k-1
+        if (interior) {
+            T F[5];
+            face_flux<RS, 2>(zprev, zm, ph, F);
+            if (want_flux && (k == 0 || k == P.nz)) {
+                T *sheet = bf + 10 * sxs + 10 * sys + (k == 0 ? 0 : 5 * szs);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sheet[q * szs + (int64_t)gj * P.nx + gi] = F[q];
+            }
+            if (k > z0) {
+                load5(uin + view.plane(k - 1) + col, view.vstride, Uold);
+                T *o = out + (int64_t)(k - 1) * P.nx * P.ny + ocol;
+                T Un[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    Un[q] = Uold[q] - dtdx * (acc[q] + F[q]);
+                    o[q * ostride] = Un[q];
+                }
+                if (want_cfl) {
+                    int unused = 0;
+                    smax = fmax(smax, cell_signal(Un, ph, unused) * inv_dx);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                acc[q] = -F[q];
+                zprev[q] = zpn[q];
+            }
+        }
+        if (post) break;
+        __syncthreads();
+
+        // ---- D: x-y flux divergence of the plane
+        if (interior) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                acc[q] = ((sm.fl[q][Geo::xface(ci + 1, cj)] - sm.fl[q][Geo::xface(ci, cj)]) +
+                          (sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] -
+                           sm.fl[yslot(q)][Geo::yface(ci, cj)])) + acc[q];
+        }
+    }
+}
+
+// One patch, one launch: tiles in z-segment-major order, remapped per XCD as
+// in the PLM step kernel.
+template <typename T, int MODE, bool CT, int RS, int TX, int TY, bool GHOSTED>
+__global__ __launch_bounds__(tile_threads(TX, TY)) __attribute__((amdgpu_waves_per_eu(2)))
+void ppm_tile_kernel(PatchDesc P, const T *__restrict__ u_in, T *__restrict__ u_out,
+                     T *__restrict__ bflux, const double *dt_dev, Scalars sc,
+                     unsigned long long *hits_ctr, int ntx, int nty, int zlen, CflOut co)
+{
+    __shared__ PpmTileSmem<T, TX, TY> sm;
+    const Phys<T> ph = make_phys<T>(sc);
+    const double dt = dt_dev ? *dt_dev : P.dt;
+    const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
+    const int nblocks = gridDim.x, b = blockIdx.x;
+    const int per_xcd = nblocks / 8;
+    const int item = b < 8 * per_xcd ? (b % 8) * per_xcd + b / 8 : b;
+    const int ntiles = ntx * nty;
+    const int seg = item / ntiles, tile = item % ntiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+    const int z0 = seg * zlen, z1 = min(z0 + zlen, P.nz);
+    int hits = 0;
+    double smax = 0.0;
+    const bool want_cfl = co.dt_next != nullptr;
+    ppm_tile<T, MODE, CT, RS, TX, TY, GHOSTED>(P, u_in, u_out, bflux, dtdx, lam, ph, x0, y0, z0, z1,
+                                               sm, hits, want_cfl, smax);
+    flush_hits(hits, hits_ctr);
+    if (want_cfl) cfl_block_max(smax, co.smax_bits);
+}
+
+template <typename T, int MODE, bool CT, int RS>
+int launch_ppm_tile_t(const PatchDesc &P, const void *u_in, void *u_out, void *bflux,
+                      const double *dt_dev, const Scalars &sc, unsigned long long *hits,
+                      int min_blocks, const CflOut &co, hipStream_t s)
+{
+    constexpr int TX = PPM_FUSED_TX, TY = PPM_FUSED_TY;
+    // periodic coordinates are wrapped twice, which covers the stencils'
+    // reach of three cells only for extents of 2 and more
+    if (P.periodic && (P.nx < 2 || P.ny < 2 || P.nz < 2)) return (int)hipErrorInvalidValue;
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    // z-ranges of 32 planes, shorter (down to one) when that leaves the chip
+    // without enough workgroups, as for the PLM step
+    int zlen = std::min(32, P.nz);
+    if (ntiles * ((P.nz + zlen - 1) / zlen) < min_blocks) {
+        const int64_t want = (min_blocks + ntiles - 1) / ntiles;
+        zlen = (int)std::min<int64_t>(zlen, std::max<int64_t>(1, (P.nz + want - 1) / want));
+    }
+    const int64_t nblocks = ntiles * ((P.nz + zlen - 1) / zlen);
+    if (nblocks <= 0 || nblocks > 0x7fffffff) return (int)hipErrorInvalidValue;
+    if (P.periodic)
+        hipLaunchKernelGGL((ppm_tile_kernel<T, MODE, CT, RS, TX, TY, false>), dim3((unsigned)nblocks),
+                           dim3(TileGeom<TX, TY>::NT), 0, s, P, (const T *)u_in, (T *)u_out,
+                           (T *)bflux, dt_dev, sc, hits, ntx, nty, zlen, co);
+    else
+        hipLaunchKernelGGL((ppm_tile_kernel<T, MODE, CT, RS, TX, TY, true>), dim3((unsigned)nblocks),
+                           dim3(TileGeom<TX, TY>::NT), 0, s, P, (const T *)u_in, (T *)u_out,
+                           (T *)bflux, dt_dev, sc, hits, ntx, nty, zlen, co);
+    return (int)hipGetLastError();
+}
+
 template <typename T, int MODE, bool CT, int RS>
 int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *pitems, int npitems,
                  const PpmItem *uitems, int nuitems, const int64_t *soff, const void *u_in,
@@ -596,6 +1041,35 @@ int launch_ppm_d(int limiter, int riemann, const PatchDesc &P1, const PatchDesc 
 }
 
 }  // namespace
+
+int launch_ppm_tile(int dtype, int limiter, int riemann, const PatchDesc &P, const void *u_in,
+                    void *u_out, void *bflux, const double *dt_dev, const Scalars &sc,
+                    unsigned long long *hits, int min_blocks, const CflOut &co, hipStream_t s)
+{
+#define GD_PPMT(T, M, C, R) return launch_ppm_tile_t<T, M, C, R>(P, u_in, u_out, bflux, dt_dev, sc, \
+                                                                 hits, min_blocks, co, s)
+#define GD_PPMT_LIM(T, C, R)                                                    \
+    do {                                                                        \
+        if (central) GD_PPMT(T, PPM_CENTRAL, C, R);                             \
+        GD_PPMT(T, PPM_LIMITED, C, R);                                          \
+    } while (0)
+#define GD_PPMT_CT(T, R)                                                        \
+    do {                                                                        \
+        if (traced) GD_PPMT_LIM(T, true, R);                                    \
+        GD_PPMT_LIM(T, false, R);                                               \
+    } while (0)
+    const bool central = limiter == 4 || limiter == 6;
+    const bool traced = limiter == 5 || limiter == 6;
+    if (dtype == 1) {
+        if (riemann == RS_HLL) GD_PPMT_CT(float, RS_HLL);
+        GD_PPMT_CT(float, RS_HLLC);
+    }
+    if (riemann == RS_HLL) GD_PPMT_CT(double, RS_HLL);
+    GD_PPMT_CT(double, RS_HLLC);
+#undef GD_PPMT_CT
+#undef GD_PPMT_LIM
+#undef GD_PPMT
+}
 
 int64_t ppm_box_cells(const PatchDesc &P)
 {

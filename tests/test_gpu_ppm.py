@@ -180,3 +180,46 @@ def test_turbulent_box_256_sampled_cells(gd, lim):
         ref, _, _ = oracle.step(blk, G, dx, dt, ng=3, limiter=lim)
         worst = max(worst, float(np.max(np.abs(got[:, z, y, x] - ref[:, 0, 0, 0]) / scale)))
     assert worst <= 1e-12, worst
+
+
+@pytest.mark.parametrize("lim", ALL)
+def test_ghost_cells_the_stencil_never_reads(gd, lim):
+    """A ghosted patch's corner ghosts and its edge ghosts deeper than (1, 2)
+    are never read: given a negative density (which any conversion of them
+    would count as a floor hit) and a NaN energy (which any use of them would
+    carry into the output), they leave the step's output, its boundary fluxes
+    and the floor count exactly as with finite values. The
+    one-launch single-patch path has interior, ring and halo columns that
+    reach three cells past a tile, so this checks that its halo and ring
+    windows stop where the reconstruction stops."""
+    nx, ny, nz, ng = 30, 11, 19, 3
+    u = inputs.random_patch(nx, ny, nz, ng=ng, seed=77, generic=True)
+    dx = 1 / 64
+    dt = oracle.cfl_dt(u, G, dx, 0.4, ng=ng)
+    # depth outside the interior along each axis, per ghosted index
+    def depth(n):
+        i = np.arange(n + 2 * ng) - ng
+        return np.where(i < 0, -i, np.where(i >= n, i - n + 1, 0))
+    dz, dy, dx_ = np.meshgrid(depth(nz), depth(ny), depth(nx), indexing="ij")
+    nout = (dz > 0).astype(int) + (dy > 0) + (dx_ > 0)
+    d = np.stack([dz, dy, dx_])
+    edge = nout == 2
+    # read: faces to depth 3, edges with depths (1, <= 2)
+    edge_read = edge & (np.sort(np.where(d > 0, d, 99), axis=0)[0] == 1) & \
+        (np.sort(np.where(d > 0, d, 0), axis=0)[2] <= 2)
+    never = (nout == 3) | (edge & ~edge_read)
+    assert never.sum() > 0
+    bad = u.copy()
+    bad[0][never] = -1.0
+    bad[4][never] = np.nan
+    ctx = gd.context()
+    say("ppm unread ghosts", lim)
+    ctx.reset_stats()
+    a, fa = gd.step(dev(u), G, dx, dt, ng=ng, limiter=lim)
+    ha = ctx.floor_hits()
+    ctx.reset_stats()
+    b, fb = gd.step(dev(bad), G, dx, dt, ng=ng, limiter=lim)
+    hb = ctx.floor_hits()
+    assert np.array_equal(host(a), host(b))
+    assert np.array_equal(host(fa), host(fb))
+    assert ha == hb
