@@ -223,9 +223,12 @@ int cfl_dt(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_patch *patches
  * of a few launches per candidate), keeps the fastest in ctx for later calls
  * of the same dtype, and returns its index in *choice (may be NULL). The
  * outputs are overwritten; the stream is synchronised. Candidates: tiles of
- * 16x16, 32x8, 8x8, 16x8 and 24x8 interior columns; z-ranges of 16, 32 and
- * 64 planes (single patch) or of 8 planes, 16 planes and the whole patch
- * (batched). */
+ * 16x16, 32x8, 8x8, 16x8 and 24x8 interior columns, and for batches also
+ * the pair 16x8 + 24x8 in one launch (each patch in the shape that covers its
+ * x-y extent with fewer padded columns, 16x8 on a tie); z-ranges of 16, 32
+ * and 64 planes (single patch) or of 8 planes, 16 planes and the whole patch
+ * (batched). The batched candidate index is 3 * (position of the shape in
+ * that list) + z policy, 0..17. */
 int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
                      const void *u_in, void *u_out, double gamma, double dx, double dt,
                      void *hip_stream, int *choice);
@@ -234,14 +237,16 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
                         void *hip_stream, int *choice);
 
 /* The configuration in use: tile shape index (0: 16x16, 1: 8x8, 2: 32x8,
- * 3: 16x8, 4: 24x8)
+ * 3: 16x8, 4: 24x8; batched also 5: the pair 16x8 + 24x8, the shape
+ * chosen per patch)
  * and z-range length (single patch) or z-range policy (batched: 0 = 8
  * planes, 1 = 16, 2 = whole patch) for dtype. */
 int gd_get_config(gd_ctx *ctx, int dtype, int *shape_single, int *zlen_single,
                   int *shape_batched, int *zpolicy_batched);
 
 /* Set the configuration explicitly (e.g. one stored from an earlier
- * autotuning run). shape in [0, 4]; zlen_single in [1, 4096];
+ * autotuning run). shape_single in [0, 4], shape_batched in [0, 5];
+ * zlen_single in [1, 4096];
  * zpolicy_batched in {0, 1, 2}. zlen_single is an upper bound: a patch that
  * would give fewer workgroups than the device holds at once is cut into
  * shorter z-ranges (down to one plane). The choice never changes results: every

@@ -341,7 +341,6 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
     if ((r = prepare_rebuild(ctx, s, c.captured, { (void **)&c.d_patches, (void **)&c.d_items },
                              { &c.cap_patches, &c.cap_items }, "batch tables")))
         return r;
-    const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
     std::vector<gd::PatchDesc> desc(npatch);
     std::vector<gd::WorkItem> items;
     std::vector<std::pair<int64_t, int>> order;     // (cells, patch): largest first
@@ -353,6 +352,8 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
     for (auto &o : order) {
         const gd_patch &p = patches[o.second];
         const int zl = batched_zlen(p.nz, zpolicy);
+        const int pshape = gd::patch_tile_shape(shape, p.nx, p.ny);
+        const int TX = gd::tile_tx(pshape), TY = gd::tile_ty(pshape);
         for (int z0 = 0; z0 < p.nz; z0 += zl)
             for (int y0 = 0; y0 < p.ny; y0 += TY)
                 for (int x0 = 0; x0 < p.nx; x0 += TX) {
@@ -360,7 +361,7 @@ int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch
                     w.patch = o.second;
                     w.x0 = (int16_t)x0; w.y0 = (int16_t)y0;
                     w.z0 = (int16_t)z0; w.z1 = (int16_t)std::min(z0 + zl, p.nz);
-                    w.shape = (int16_t)shape;
+                    w.shape = (int16_t)pshape;
                     items.push_back(w);
                 }
     }
@@ -925,15 +926,15 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
     if (capturing((hipStream_t)hip_stream))
         return fail(ctx, GD_E_UNSUPPORTED, "the autotuner waits on the host and cannot be captured");
     const int dt_i = opts->dtype;
-    const int shapes[5] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
-                            gd::TILE_24x8 };
+    const int shapes[6] = { gd::TILE_16x16, gd::TILE_32x8, gd::TILE_8x8, gd::TILE_16x8,
+                            gd::TILE_24x8, gd::TILE_PAIR_24x8 };
     const int keep_shape = ctx->shape_batched[dt_i], keep_pol = ctx->zpolicy_batched[dt_i];
     // the same protocol as gd_autotune_step: a warm-up round, then the best
     // of two timed rounds per candidate
-    float best_ms[15];
+    float best_ms[18];
     for (float &m : best_ms) m = 1e30f;
     for (int round = 0; round < 3; ++round)
-        for (int c = 0; c < 15; ++c) {
+        for (int c = 0; c < 18; ++c) {
             ctx->shape_batched[dt_i] = shapes[c / 3];
             ctx->zpolicy_batched[dt_i] = c % 3;
             float ms = 0.f;
@@ -949,7 +950,7 @@ int gd_autotune_batched(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_p
             if (round > 0) best_ms[c] = std::min(best_ms[c], ms);
         }
     int best_i = 0;
-    for (int c = 1; c < 15; ++c)
+    for (int c = 1; c < 18; ++c)
         if (best_ms[c] < best_ms[best_i]) best_i = c;
     ctx->shape_batched[dt_i] = shapes[best_i / 3];
     ctx->zpolicy_batched[dt_i] = best_i % 3;
@@ -975,7 +976,7 @@ int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int
     if (!ctx) return fail(ctx, GD_E_ARG, "ctx is NULL");
     if (dtype != GD_F64 && dtype != GD_F32) return fail(ctx, GD_E_ARG, "bad dtype %d", dtype);
     if (shape_single < 0 || shape_single >= gd::NUM_TILE_SHAPES || shape_batched < 0 ||
-        shape_batched >= gd::NUM_TILE_SHAPES)
+        shape_batched >= gd::NUM_BATCHED_SHAPES)
         return fail(ctx, GD_E_ARG, "bad tile shape");
     if (zlen_single < 1 || zlen_single > 4096) return fail(ctx, GD_E_ARG, "bad z-range length");
     if (zpolicy_batched < 0 || zpolicy_batched > 2) return fail(ctx, GD_E_ARG, "bad z-range policy");
@@ -1489,7 +1490,6 @@ int build_stream_plan(gd_ctx *ctx, gd_stream_state &st, const gd_opts *opts, int
         std::memcmp(st.host.data(), patches, npatch * sizeof(gd_patch)) == 0)
         return GD_OK;
     const size_t es = elem_size(opts);
-    const int TX = gd::tile_tx(shape), TY = gd::tile_ty(shape);
     // patches in host-memory order of their inputs, so that packed batches
     // copy in one run per chunk and buffer
     std::vector<int> order(npatch);
@@ -1530,6 +1530,8 @@ int build_stream_plan(gd_ctx *ctx, gd_stream_state &st, const gd_opts *opts, int
             const int pidx = (int)desc.size();
             desc.push_back(d);
             const int zl = batched_zlen(p.nz, zp);
+            const int pshape = gd::patch_tile_shape(shape, p.nx, p.ny);
+            const int TX = gd::tile_tx(pshape), TY = gd::tile_ty(pshape);
             for (int z0 = 0; z0 < p.nz; z0 += zl)
                 for (int y0 = 0; y0 < p.ny; y0 += TY)
                     for (int x0 = 0; x0 < p.nx; x0 += TX) {
@@ -1537,7 +1539,7 @@ int build_stream_plan(gd_ctx *ctx, gd_stream_state &st, const gd_opts *opts, int
                         w.patch = pidx;
                         w.x0 = (int16_t)x0; w.y0 = (int16_t)y0;
                         w.z0 = (int16_t)z0; w.z1 = (int16_t)std::min(z0 + zl, p.nz);
-                        w.shape = (int16_t)shape;
+                        w.shape = (int16_t)pshape;
                         items.push_back(w);
                     }
             ++c.npatch;

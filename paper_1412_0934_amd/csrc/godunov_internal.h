@@ -29,11 +29,17 @@ struct WorkItem {
 
 // Tile shapes the forward kernels are instantiated for (interior columns
 // TX x TY of one workgroup).
+// TILE_PAIR_24x8 is a batched-only choice: one launch that steps each patch
+// in 24x8 tiles where they cover its x-y extent with fewer padded columns than
+// 16x8 tiles do, and in 16x8 tiles otherwise, in 256-thread workgroups.
 enum TileShape : int {
-    TILE_16x16 = 0, TILE_8x8 = 1, TILE_32x8 = 2, TILE_16x8 = 3, TILE_24x8 = 4, NUM_TILE_SHAPES = 5
+    TILE_16x16 = 0, TILE_8x8 = 1, TILE_32x8 = 2, TILE_16x8 = 3, TILE_24x8 = 4, NUM_TILE_SHAPES = 5,
+    TILE_PAIR_24x8 = 5, NUM_BATCHED_SHAPES = 6
 };
 int tile_tx(int shape);
 int tile_ty(int shape);
+// the concrete shape that a batched launch of `shape` uses on a patch
+int patch_tile_shape(int shape, int nx, int ny);
 
 struct Scalars {
     double gamma, rho_floor, p_floor;

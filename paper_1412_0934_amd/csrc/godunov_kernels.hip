@@ -40,6 +40,22 @@ int tile_ty(int shape)
     default: return 16;
     }
 }
+int patch_tile_shape(int shape, int nx, int ny)
+{
+    if (shape != TILE_PAIR_24x8) return shape;
+    const int other = TILE_24x8;
+    auto padded = [&](int sh) {
+        const int tx = tile_tx(sh), ty = tile_ty(sh);
+        return (int64_t)((nx + tx - 1) / tx * tx) * ((ny + ty - 1) / ty * ty);
+    };
+    return padded(other) < padded(TILE_16x8) ? other : TILE_16x8;
+}
+
+// workgroup size of a pair kernel: the larger of the two tiles'
+constexpr int pair_threads(int txb, int tyb)
+{
+    return tile_threads(txb, tyb) > tile_threads(16, 8) ? tile_threads(txb, tyb) : tile_threads(16, 8);
+}
 
 
 __global__ __launch_bounds__(64) void cfl_finalize_kernel(double cfl, double *dt_out,
@@ -109,6 +125,57 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_batched_kernel
         const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
         godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0,
                                          w.z1, sm, hits, want_cfl, smax);
+        __syncthreads();
+    }
+    flush_hits(hits, hits_ctr);
+    if (want_cfl) cfl_block_max(smax, co.smax_bits);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned done = atomicAdd(&queue[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
+    }
+}
+
+// A batch in two tile shapes: the same work queue, each item naming its
+// shape (A = 16x8 or B). Workgroups are sized for the larger tile; a thread
+// that owns no column of a smaller tile only shares the staging and the face
+// solves. The two shapes' LDS buffers overlap.
+template <typename T, int LIM, int RS, int TXB, int TYB>
+__global__ __launch_bounds__(pair_threads(TXB, TYB))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_batched_pair_kernel(
+    const PatchDesc *__restrict__ patches, const WorkItem *__restrict__ items, int nitems,
+    const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ bflux,
+    const double *dt_dev, Scalars sc, unsigned long long *hits_ctr, unsigned *queue, CflOut co)
+{
+    constexpr int NT = pair_threads(TXB, TYB);
+    __shared__ union {
+        TileSmem<T, 16, 8> a;
+        TileSmem<T, TXB, TYB> b;
+    } sm;
+    __shared__ int s_item;
+    const Phys<T> ph = make_phys<T>(sc);
+    int hits = 0;
+    double smax = 0.0;
+    const bool want_cfl = co.dt_next != nullptr;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const PatchDesc P = patches[w.patch];
+        const double dt = dt_dev ? *dt_dev : P.dt;
+        const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
+        if (w.shape == TILE_16x8)
+            godunov_tile<T, LIM, RS, 16, 8, NT>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0,
+                                                w.z0, w.z1, sm.a, hits, want_cfl, smax);
+        else
+            godunov_tile<T, LIM, RS, TXB, TYB, NT>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0,
+                                                   w.y0, w.z0, w.z1, sm.b, hits, want_cfl, smax);
         __syncthreads();
     }
     flush_hits(hits, hits_ctr);
@@ -240,6 +307,21 @@ static int dispatch_shape_step(int shape, const PatchDesc &P, const void *u_in, 
     }
 }
 
+template <typename T, int LIM, int RS, int TXB, int TYB>
+static int launch_batched_pair_t(const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
+                                 const void *u_in, void *u_out, void *bflux, const double *dt_dev,
+                                 const Scalars &sc, unsigned long long *hits, unsigned *d_queue,
+                                 int grid, const CflOut &co, hipStream_t s)
+{
+    hipLaunchKernelGGL((step_batched_pair_kernel<T, LIM, RS, TXB, TYB>), dim3(grid),
+                       dim3(pair_threads(TXB, TYB)), 0, s, d_patches, d_items, nitems,
+                       (const T *)u_in, (T *)u_out, (T *)bflux, dt_dev, sc, hits, d_queue, co);
+    if (co.dt_next)
+        hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, co.cfl, co.dt_next,
+                           co.smax_bits);
+    return (int)hipGetLastError();
+}
+
 template <typename T, int LIM, int RS>
 static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const WorkItem *d_items,
                                   int nitems, const void *u_in, void *u_out, void *bflux,
@@ -252,6 +334,7 @@ static int dispatch_shape_batched(int shape, const PatchDesc *d_patches, const W
     case TILE_32x8: return launch_batched_t<T, LIM, RS, 32, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     case TILE_16x8: return launch_batched_t<T, LIM, RS, 16, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     case TILE_24x8: return launch_batched_t<T, LIM, RS, 24, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
+    case TILE_PAIR_24x8: return launch_batched_pair_t<T, LIM, RS, 24, 8>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     default: return launch_batched_t<T, LIM, RS, 16, 16>(d_patches, d_items, nitems, u_in, u_out, bflux, dt_dev, sc, hits, d_queue, grid, co, s);
     }
 }
@@ -339,6 +422,9 @@ static int occupancy_t(int shape, int device)
         break;
     case TILE_24x8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 24, 8>, TileGeom<24, 8>::NT, 0);
+        break;
+    case TILE_PAIR_24x8:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_pair_kernel<T, LIM, RS, 24, 8>, pair_threads(24, 8), 0);
         break;
     default:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batched_kernel<T, LIM, RS, 16, 16>, TileGeom<16, 16>::NT, 0);

@@ -266,8 +266,9 @@ int na_launch_t(const gd_patch *patches, int npatch, const void *u_in, void *u_o
     return (int)hipGetLastError();
 }
 
-// FP64 on 16x8 tiles, FP32 on 24x8 tiles: the shapes the autotuner picks for
-// batches of 8^3..32^3 patches. Results do not depend on the shape.
+// FP64 on 16x8 tiles (the shape the autotuner picks for batches of
+// 8^3..32^3 patches), FP32 on 24x8 tiles (within about 5% of the 16x8 + 24x8
+// pair it picks there). Results do not depend on the shape.
 template <typename T, int LIM, int RS>
 int na_launch_shape(const gd_patch *patches, int npatch, const void *u_in, void *u_out, void *bflux,
                     const double *dt_dev, const Scalars &sc, const NaDevice &d, hipStream_t s)

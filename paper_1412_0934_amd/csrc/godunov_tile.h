@@ -17,10 +17,14 @@ namespace gd {
 // columns, rounded up to whole waves (24x8: 192 + 64 = 256 threads, 4 waves).
 constexpr int tile_threads(int tx, int ty) { return ((tx * ty + 2 * (tx + ty) + 63) / 64) * 64; }
 
-template <int TX, int TY>
+// NT, the workgroup size, may exceed tile_threads(TX, TY) (a kernel that runs
+// tiles of several shapes in one workgroup size); the surplus threads own no
+// column and only share the staging and face work.
+template <int TX, int TY, int NT_ = tile_threads(TX, TY)>
 struct TileGeom {
+    static_assert(NT_ >= tile_threads(TX, TY), "workgroup too small for the tile");
     static constexpr int NINT = TX * TY;
-    static constexpr int NT = tile_threads(TX, TY);
+    static constexpr int NT = NT_;
     // faces of a plane: the x faces i-1/2 (i = 0..TX) of each row, then the y
     // faces j-1/2 (j = 0..TY) of each column
     static constexpr int NXF = TY * (TX + 1);
@@ -163,13 +167,13 @@ enum { ROLE_NONE = -1, ROLE_INT = 0, ROLE_BOTTOM = 1, ROLE_TOP = 2, ROLE_LEFT = 
 //      face once; then interior columns: the z face below the plane, which
 //      completes plane k-1;
 //   D  interior: x-y flux divergence accumulated for plane k.
-template <typename T, int LIM, int RS, int TX, int TY>
+template <typename T, int LIM, int RS, int TX, int TY, int NT = tile_threads(TX, TY)>
 __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
                              T *__restrict__ u_out_base, T *__restrict__ bflux_base, T dtdx, T lam,
                              const Phys<T> &ph, int x0, int y0, int z0, int z1,
                              TileSmem<T, TX, TY> &sm, int &hits, bool want_cfl, double &smax)
 {
-    using Geo = TileGeom<TX, TY>;
+    using Geo = TileGeom<TX, TY, NT>;
     constexpr int NF = Geo::NF;
     const int tid = threadIdx.x;
     const int ax = min(TX, P.nx - x0);

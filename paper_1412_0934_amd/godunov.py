@@ -476,6 +476,8 @@ def step_adjoint(u, lam_out, gamma, dx, dt, *, lam_bflux=None, ng=2, periodic=Fa
 
 
 TILE_SHAPES = ("16x16", "8x8", "32x8", "16x8", "24x8")
+# a batched launch may also pair 16x8 and 24x8 tiles, the shape chosen per patch
+BATCHED_SHAPES = TILE_SHAPES + ("16x8+24x8",)
 
 
 def autotune_step(u, gamma, dx, dt, *, ng=2, periodic=False, limiter="minmod", riemann="hllc",
@@ -519,14 +521,14 @@ def get_config(dtype=torch.float64) -> dict:
     v = [ctypes.c_int() for _ in range(4)]
     ctx.check(ctx.lib.gd_get_config(ctx.handle, DTYPES[dtype], *[ctypes.byref(x) for x in v]))
     return {"shape_single": TILE_SHAPES[v[0].value], "zlen_single": v[1].value,
-            "shape_batched": TILE_SHAPES[v[2].value], "zpolicy_batched": v[3].value}
+            "shape_batched": BATCHED_SHAPES[v[2].value], "zpolicy_batched": v[3].value}
 
 
 def set_config(dtype=torch.float64, *, shape_single="16x16", zlen_single=32,
                shape_batched="16x16", zpolicy_batched=1) -> None:
     ctx = context()
     ctx.check(ctx.lib.gd_set_config(ctx.handle, DTYPES[dtype], TILE_SHAPES.index(shape_single),
-                                    int(zlen_single), TILE_SHAPES.index(shape_batched),
+                                    int(zlen_single), BATCHED_SHAPES.index(shape_batched),
                                     int(zpolicy_batched)))
 
 

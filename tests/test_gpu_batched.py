@@ -172,14 +172,15 @@ def check_telescoping(batch, out, flux, dt):
 
 
 @pytest.mark.parametrize("dtype_name,shape,policy", [
-    ("f64", "16x16", 1), ("f64", "16x8", 2), ("f64", "24x8", 2),
-    ("f32", "16x16", 1), ("f32", "24x8", 2), ("f32", "16x8", 2)])
+    ("f64", "16x16", 1), ("f64", "16x8", 2), ("f64", "24x8", 2), ("f64", "16x8+24x8", 2),
+    ("f32", "16x16", 1), ("f32", "24x8", 2), ("f32", "16x8", 2), ("f32", "16x8+24x8", 2)])
 def test_full_amr_batch(gd, amr, dtype_name, shape, policy):
     """4096 patches 8^3..32^3 in one persistent launch, in the default
     configuration and in the ones the autotuner picks for this batch on one
-    MI355X (FP64: 16x8 tiles, FP32: 24x8 tiles, whole-patch z-ranges, which
-    the benchmark times), every patch against the oracle element by element,
-    and (FP64) the boundary-flux telescoping identity on every patch."""
+    MI355X (FP64: 16x8 tiles, FP32: the 16x8 + 24x8 pair, whole-patch
+    z-ranges, which the benchmark times), every patch against the oracle
+    element by element, and (FP64) the boundary-flux telescoping identity on
+    every patch."""
     import torch
     batch, dt, ref_out, ref_flux = amr
     dtype = torch.float64 if dtype_name == "f64" else torch.float32

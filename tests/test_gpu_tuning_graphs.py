@@ -77,7 +77,7 @@ def test_every_batched_configuration_gives_identical_bits(gd):
     u_in = torch.from_numpy(batch.u_in).cuda()
     results = []
     try:
-        for shape in gd.TILE_SHAPES:
+        for shape in gd.BATCHED_SHAPES:
             for pol in (0, 1, 2):
                 say("batched config", shape, pol)
                 gd.set_config(torch.float64, shape_batched=shape, zpolicy_batched=pol)
@@ -89,6 +89,20 @@ def test_every_batched_configuration_gives_identical_bits(gd):
         gd.set_config(torch.float64)
     for out, flux in results[1:]:
         assert np.array_equal(out, results[0][0]) and np.array_equal(flux, results[0][1])
+
+
+def test_the_tile_pair_is_a_batched_only_choice(gd):
+    """gd_set_config takes the 16x8 + 24x8 pair (index 5) as a batched shape
+    only; a single-patch shape 5 or a batched shape 6 is an argument error."""
+    import torch
+    ctx = gd.context()
+    try:
+        assert ctx.lib.gd_set_config(ctx.handle, 0, 5, 32, 3, 1) != 0
+        assert ctx.lib.gd_set_config(ctx.handle, 0, 3, 32, 6, 1) != 0
+        assert ctx.lib.gd_set_config(ctx.handle, 1, 3, 32, 5, 2) == 0
+        assert gd.get_config(torch.float32)["shape_batched"] == "16x8+24x8"
+    finally:
+        gd.set_config(torch.float32)
 
 
 def test_autotuner_picks_a_configuration_that_keeps_parity(gd):
