@@ -65,7 +65,8 @@ struct Geo {
 // Per-cell records of 20 doubles, stored in blocks of 64 consecutive cells
 // with the fields of a block contiguous ([E/64][20][64]): a wavefront reads
 // one field of 64 neighbouring cells as one 512-byte segment, and all the
-// fields of those cells lie in one 10 KB span.
+// fields of those cells lie in one 10 KB span. Records are written with
+// streaming (non-temporal) stores: the next kernel reads them long after.
 constexpr int NF = 20;
 // fields of the forward record: slopes S at d*5+q, predicted state W* at 15+q
 constexpr int F_S = 0, F_WS = 15;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void k_predict(Geo g, const double *__restrict
             const double a = W[q] - Wm[q], b = Wp[q] - W[q];
             S[d][q] = slope<LIM>(a, b);
             code |= slope_branch<LIM>(a, b) << (2 * (d * 5 + q));
-            s.fw[rec(e, F_S + d * 5 + q)] = S[d][q];
+            __builtin_nontemporal_store(S[d][q], &s.fw[rec(e, F_S + d * 5 + q)]);
         }
     }
     s.code[e] = code;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void k_predict(Geo g, const double *__restrict
     Ws[2] = W[2] - g.lam * (adv[2] + S[1][4] * inv_rho);
     Ws[3] = W[3] - g.lam * (adv[3] + S[2][4] * inv_rho);
     Ws[4] = W[4] - g.lam * (adv[4] + g.gamma * W[4] * divu);
-    for (int q = 0; q < 5; ++q) s.fw[rec(e, F_WS + q)] = Ws[q];
+    for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(Ws[q], &s.fw[rec(e, F_WS + q)]);
 }
 
 // ------------------------------------------------------------ Riemann adjoints
@@ -719,9 +720,10 @@ __global__ __launch_bounds__(CT) void k_cells(Geo g, const double *__restrict__ 
         Sb[1][2] += divub;
         Sb[2][3] += divub;
         for (int d = 0; d < 3; ++d) Wb[1 + d] += velb[d];
-        for (int q = 0; q < 5; ++q) s.ad[rec(e, F_WD + q)] = Wb[q];
+        for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(Wb[q], &s.ad[rec(e, F_WD + q)]);
         for (int d = 0; d < 3; ++d)
-            for (int q = 0; q < 5; ++q) s.ad[rec(e, F_SB + d * 5 + q)] = Sb[d][q];
+            for (int q = 0; q < 5; ++q)
+                __builtin_nontemporal_store(Sb[d][q], &s.ad[rec(e, F_SB + d * 5 + q)]);
     }
 }
 
@@ -821,7 +823,7 @@ __global__ __launch_bounds__(256) void k_input(Geo g, const double *__restrict__
     for (int q = 0; q < 5; ++q) {
         double v = Ub[q];
         if (inside) v += lam_out[q * g.nint + ii];
-        lam_in[c + q * g.vin] = v;
+        __builtin_nontemporal_store(v, &lam_in[c + q * g.vin]);
     }
 }
 

@@ -123,8 +123,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_batched_kernel
         const PatchDesc P = patches[w.patch];
         const double dt = dt_dev ? *dt_dev : P.dt;
         const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
-        godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0,
-                                         w.z1, sm, hits, want_cfl, smax);
+        godunov_tile<T, LIM, RS, TX, TY, tile_threads(TX, TY), true>(
+            P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0, w.z1, sm, hits, want_cfl, smax);
         __syncthreads();
     }
     flush_hits(hits, hits_ctr);
@@ -171,10 +171,10 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void step_batched_pair_k
         const double dt = dt_dev ? *dt_dev : P.dt;
         const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
         if (w.shape == TILE_16x8)
-            godunov_tile<T, LIM, RS, 16, 8, NT>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0,
+            godunov_tile<T, LIM, RS, 16, 8, NT, true>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0,
                                                 w.z0, w.z1, sm.a, hits, want_cfl, smax);
         else
-            godunov_tile<T, LIM, RS, TXB, TYB, NT>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0,
+            godunov_tile<T, LIM, RS, TXB, TYB, NT, true>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0,
                                                    w.y0, w.z0, w.z1, sm.b, hits, want_cfl, smax);
         __syncthreads();
     }

@@ -358,8 +358,9 @@ __global__ __launch_bounds__(256) void k_predict(Par<T> P, const T *__restrict__
         to_prim<false>(P, Ud, Wd);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            fs[(size_t)((d * 2 + 0) * NV + q) * P.n + c] = Wu[q];
-            fs[(size_t)((d * 2 + 1) * NV + q) * P.n + c] = Wd[q];
+            // streamed out: the sweep reads each value back once, long after
+            __builtin_nontemporal_store(Wu[q], &fs[(size_t)((d * 2 + 0) * NV + q) * P.n + c]);
+            __builtin_nontemporal_store(Wd[q], &fs[(size_t)((d * 2 + 1) * NV + q) * P.n + c]);
         }
     }
 }
@@ -388,7 +389,8 @@ __device__ __forceinline__ void load_state(const Par<T> &P, const T *__restrict_
                                            int side, int c, T W[NV])
 {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) W[q] = fs[(size_t)((d * 2 + side) * NV + q) * P.n + c];
+    for (int q = 0; q < NV; ++q)
+        W[q] = __builtin_nontemporal_load(&fs[(size_t)((d * 2 + side) * NV + q) * P.n + c]);
 }
 
 // Faces of one direction: slot s of the x pass is row s / (MTX+1), face
@@ -488,7 +490,7 @@ void k_sweep(Par<T> P, const T *__restrict__ dyn,
                 const T dFz = Fhi[q] - Flo[q];
                 T v = u[(size_t)q * P.n + c] - P.c * ((dFx[q] + dFy[q]) + dFz);
                 if (q == 8) v *= P.damp;
-                out[(size_t)q * P.n + c] = v;
+                __builtin_nontemporal_store(v, &out[(size_t)q * P.n + c]);
                 U[q] = v;
             }
             if (acc) {

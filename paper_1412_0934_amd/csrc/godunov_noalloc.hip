@@ -230,8 +230,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<T>()))) void na_step_kernel(
         P.dx = g.dx; P.dt = g.dt;
         const double dt = dt_dev ? *dt_dev : P.dt;
         const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
-        godunov_tile<T, LIM, RS, TX, TY>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0,
-                                         w.z1, sm, hits, false, smax);
+        godunov_tile<T, LIM, RS, TX, TY, tile_threads(TX, TY), true>(
+            P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0, w.z0, w.z1, sm, hits, false, smax);
         __syncthreads();
     }
     flush_hits(hits, &scr[3]);

@@ -167,7 +167,14 @@ enum { ROLE_NONE = -1, ROLE_INT = 0, ROLE_BOTTOM = 1, ROLE_TOP = 2, ROLE_LEFT = 
 //      face once; then interior columns: the z face below the plane, which
 //      completes plane k-1;
 //   D  interior: x-y flux divergence accumulated for plane k.
-template <typename T, int LIM, int RS, int TX, int TY, int NT = tile_threads(TX, TY)>
+// STREAM_OUT: write the new state with streaming (non-temporal) stores. The
+// batched launches do: there the outputs of many small patches would
+// otherwise evict from the L2 the inputs that neighbouring tiles still read
+// (7% fewer bytes fetched on the 4096-patch batch, 1.5% faster). A single
+// patch keeps ordinary stores: streaming ones raised its write traffic by 8%
+// (rows that two tiles share are no longer merged in the L2) at no gain.
+template <typename T, int LIM, int RS, int TX, int TY, int NT = tile_threads(TX, TY),
+          bool STREAM_OUT = false>
 __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
                              T *__restrict__ u_out_base, T *__restrict__ bflux_base, T dtdx, T lam,
                              const Phys<T> &ph, int x0, int y0, int z0, int z1,
@@ -415,7 +422,10 @@ __device__ void godunov_tile(const PatchDesc &P, const T *__restrict__ u_in_base
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     Un[q] = Uold[q] - dtdx * (acc[q] + F[q]);
-                    o[q * ostride] = Un[q];
+                    if constexpr (STREAM_OUT)
+                        __builtin_nontemporal_store(Un[q], &o[q * ostride]);
+                    else
+                        o[q * ostride] = Un[q];
                 }
                 if (want_cfl) {
                     // signal speed of the new state, exactly as cfl_dt computes it
