@@ -435,9 +435,10 @@ def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
 
 def bench_ppm(torch, gd, u0, steps=10, warmup=2, limiter="ppm"):
     """The 256^3 periodic box with the PPM reconstruction (limited parabola,
-    HLLC): per step one godunov_step_cfl (predict and update launches, then
-    the CFL reduction of the new state), dt in a device scalar; with the
-    Hancock half step (limiter "ppm") or characteristic tracing ("ppm_ct")."""
+    HLLC): per step one godunov_step_cfl (one launch: the tile march with the
+    parabola, the update and the CFL reduction of the new state), dt in a
+    device scalar; with the Hancock half step (limiter "ppm") or
+    characteristic tracing ("ppm_ct")."""
     n = u0.shape[1]
     log(f"bench: PPM ({limiter}), {n}^3 periodic box")
     dx = 1.0 / n
@@ -467,10 +468,66 @@ def bench_ppm(torch, gd, u0, steps=10, warmup=2, limiter="ppm"):
     half = "characteristic tracing" if limiter == "ppm_ct" else "Hancock half step"
     return {"workload": f"periodic Euler box {n}^3 FP64 (the turbulent box of the main line), "
                         f"PPM reconstruction (limited parabola) + {half} + HLLC; per step "
-                        "one godunov_step_cfl (predict, update, CFL reduction), dt on the device",
+                        "one godunov_step_cfl (one launch: reconstruction, update, CFL reduction), "
+                        "dt on the device",
             "ms_per_step": round(ms, 4), "mcell_per_s": cells / (ms * 1e-3) / 1e6,
             "bytes_per_step": 80 * cells, "achieved_gbs": 80 * cells / (ms * 1e-3) / 1e9,
             "hbm_frac": 80 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_ppm_batched(torch, gd, limiter, steps=10, warmup=2):
+    """1024 ghost-zoned patches of 8^3..32^3 (ng = 3) with the PPM
+    reconstruction, FP64: per step one godunov_step_batched_cfl (one
+    persistent launch and the CFL finish), boundary fluxes returned."""
+    import numpy as np
+    from paper_1412_0934_amd import inputs
+    log(f"bench: PPM ({limiter}) batch of 1024 patches")
+    batch = bench_ppm_batched.cache
+    if batch is None:
+        batch = inputs.amr_batch(1024, seed=5, ng=3)
+        bench_ppm_batched.cache = batch
+    table = gd.patch_table(batch.dims, 3, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, 0.0)
+    u_in = torch.from_numpy(batch.u_in).cuda()
+    out = torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda")
+    flux = torch.empty(batch.flux_size, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.cfl_dt_batched(u_in, table, GAMMA, 0.4, out=dt)
+    dt_next = torch.empty_like(dt)
+
+    def one():
+        gd.step_batched(u_in, table, GAMMA, out=out, bflux=flux, dt_dev=dt, limiter=limiter,
+                        cfl=0.4, dt_next=dt_next)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = batch.interior_cells
+    # minimal traffic: the cells the stencils read once (the interior, face
+    # ghosts to depth 3, edge ghosts at depths (1, 1), (1, 2) and (2, 1)), the
+    # interior written once and the boundary-flux sheets written once
+    d = batch.dims.astype(np.int64)
+    read_cells = (np.prod(d, axis=1) + 6 * (d[:, 0] * d[:, 1] + d[:, 1] * d[:, 2] + d[:, 0] * d[:, 2])
+                  + 12 * (d[:, 0] + d[:, 1] + d[:, 2])).sum()
+    nbytes = 8 * (5 * read_cells + 5 * cells + batch.flux_size)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    half = "characteristic tracing" if limiter == "ppm_ct" else "Hancock half step"
+    return {"workload": "1024 ghost-zoned patches 8^3..32^3 (p=.5/.3/.15/.05), ng=3, FP64, PPM "
+                        f"(limited parabola) + {half} + HLLC, bflux returned; one persistent launch",
+            "cells": int(cells), "ms_per_step": round(ms, 4),
+            "mcell_per_s": cells / (ms * 1e-3) / 1e6, "bytes_per_step": int(nbytes),
+            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
+bench_ppm_batched.cache = None
 
 
 def bench_streamed(torch, gd, steps=5, chunks=(64 << 20, 256 << 20)):
@@ -953,6 +1010,7 @@ def main():
     if not args.no_ppm:
         also["ppm"] = bench_ppm(torch, gd, r["u0"])
         also["ppm_ct"] = bench_ppm(torch, gd, r["u0"], limiter="ppm_ct")
+        also["ppm_batched"] = [bench_ppm_batched(torch, gd, lim) for lim in ("ppm", "ppm_ct")]
     if not args.no_streamed:
         also["streamed"] = bench_streamed(torch, gd)
     if not args.no_adjoint:

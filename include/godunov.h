@@ -317,14 +317,14 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
  * smooth data for the unlimited parabola).
  * A ghosted patch needs ng >= 3 (GD_E_ARG otherwise): the stencil reads face
  * ghosts to depth 3 and edge ghosts at depths (1, <= 2); corners never.
- * godunov_step(_cfl) runs a patch in one launch with no scratch (and reduces
- * the new state's CFL step in the same pass), except a periodic box with an
- * extent below 2. That box and godunov_step_batched(_cfl) use two launches
- * over a device scratch of 30 values per cell of the patch's box extended by
- * one layer (the periodic box itself), grown on first use (the growth
- * synchronises the device); their _cfl entry points reduce the CFL step in a
- * separate launch after the step. The adjoint, the autotuner, the MHD step
- * and the AMR seams return GD_E_UNSUPPORTED for PPM. */
+ * godunov_step(_cfl) runs a patch, and godunov_step_batched(_cfl) a batch, in
+ * one launch with no scratch (and reduces the new state's CFL step in the
+ * same pass), except a periodic box with an extent below 2. That box uses two
+ * launches over a device scratch of 30 values per cell of the box, grown on
+ * first use (the growth synchronises the device); its _cfl entry point
+ * reduces the CFL step in a separate launch after the step. The adjoint, the
+ * autotuner, the MHD step and the AMR seams return GD_E_UNSUPPORTED for
+ * PPM. */
 
 /* ------------------------------------------------------------ ideal MHD
  *

@@ -29,19 +29,6 @@ struct BatchCache {
     bool captured = false;            // a stream capture used these tables
 };
 
-struct PpmCache {
-    std::vector<gd_patch> host;
-    int dtype = -1;
-    gd::PatchDesc *d_patches = nullptr;
-    gd::PpmTile *d_pitems = nullptr;
-    gd::PpmItem *d_uitems = nullptr;
-    int64_t *d_soff = nullptr;
-    int npitems = 0, nuitems = 0;
-    int64_t scratch_elems = 0;
-    size_t cap_patches = 0, cap_pitems = 0, cap_uitems = 0, cap_soff = 0;
-    bool captured = false;
-};
-
 // Scratch memory grown on demand. A buffer that a stream capture used is
 // never freed before gd_destroy: a graph made from that capture still reads it.
 struct Scratch {
@@ -92,13 +79,12 @@ struct gd_ctx {
     std::vector<hipStream_t> slot_stream;   // stream of each assigned slot
     unsigned slot_shared = 0;               // round robin beyond NSLOT streams
     BatchCache batch;
+    BatchCache ppm_batch;                // work items of the fused PPM batched step
     BatchCache cfl;                      // descriptor cache used by cfl_dt
     Scratch adj;                         // adjoint scratch (grown on demand)
     Scratch mhd;                         // MHD step scratch (grown on demand)
     Scratch ppm_s;                       // PPM face-state scratch (grown on demand)
     std::vector<void *> retired;         // captured buffers replaced since; freed at destroy
-    PpmCache ppm;                        // batch tables of the PPM step
-    BatchCache ppm_cfl;                  // CFL tables over the PPM batch's outputs
     gd_stream_state *stream = nullptr;   // streamed batches (created on first use)
     // tuned configuration per dtype (index 0: FP64, 1: FP32)
     int zlen_single[2] = { 32, 32 };
@@ -320,18 +306,21 @@ gd::PatchDesc to_desc(const gd_patch &p, bool periodic)
 // two extra planes a march reads, short enough to spread a patch over
 // several workgroups.
 // Policies: 0 = ranges of 8 planes, 1 = ranges of 16 planes (a patch of up
-// to 32 planes is split in two), 2 = the whole patch in one range.
+// to 32 planes is split in two), 2 = the whole patch in one range, 3 (the
+// PPM march, whose window reaches three planes past a range) = ranges of up
+// to 32 planes.
 int batched_zlen(int nz, int policy)
 {
     if (policy == 0) return std::min(nz, 8);
     if (policy == 2) return nz;
+    if (policy == 3) return std::min(nz, 32);
     return nz <= 16 ? nz : (nz <= 32 ? (nz + 1) / 2 : 16);
 }
 
 int build_step_tables(gd_ctx *ctx, int dtype, int shape, int zpolicy, int npatch,
-                      const gd_patch *patches, hipStream_t s)
+                      const gd_patch *patches, hipStream_t s, BatchCache *cache = nullptr)
 {
-    BatchCache &c = ctx->batch;
+    BatchCache &c = cache ? *cache : ctx->batch;
     const int tag = dtype * 16 + zpolicy;
     if (c.dtype == tag && c.shape == shape && same_patches(c, npatch, patches)) {
         if (capturing(s)) c.captured = true;
@@ -463,7 +452,7 @@ int gd_destroy(gd_ctx *ctx)
     if (!ctx) return GD_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (BatchCache *c : { &ctx->batch, &ctx->cfl }) {
+    for (BatchCache *c : { &ctx->batch, &ctx->ppm_batch, &ctx->cfl }) {
         if (c->d_patches) (void)hipFree(c->d_patches);
         if (c->d_items) (void)hipFree(c->d_items);
         if (c->d_cfl_items) (void)hipFree(c->d_cfl_items);
@@ -471,12 +460,6 @@ int gd_destroy(gd_ctx *ctx)
     for (Scratch *sc : { &ctx->adj, &ctx->mhd, &ctx->ppm_s })
         if (sc->p) (void)hipFree(sc->p);
     for (void *p : ctx->retired) (void)hipFree(p);
-    if (ctx->ppm.d_patches) (void)hipFree(ctx->ppm.d_patches);
-    if (ctx->ppm.d_pitems) (void)hipFree(ctx->ppm.d_pitems);
-    if (ctx->ppm.d_uitems) (void)hipFree(ctx->ppm.d_uitems);
-    if (ctx->ppm.d_soff) (void)hipFree(ctx->ppm.d_soff);
-    if (ctx->ppm_cfl.d_patches) (void)hipFree(ctx->ppm_cfl.d_patches);
-    if (ctx->ppm_cfl.d_cfl_items) (void)hipFree(ctx->ppm_cfl.d_cfl_items);
     free_stream_state(ctx->stream);
     if (ctx->d_u64) (void)hipFree(ctx->d_u64);
     if (ctx->d_u32) (void)hipFree(ctx->d_u32);
@@ -521,61 +504,6 @@ namespace {
 int ensure_ppm_scratch(gd_ctx *ctx, size_t need, hipStream_t s)
 {
     return ensure_scratch(ctx, ctx->ppm_s, need, s, "PPM");
-}
-
-// Work tables of a PPM batch: 256-cell pieces of each patch's scratch box
-// (predict) and of its interior (update), and each patch's scratch offset.
-int build_ppm_tables(gd_ctx *ctx, int npatch, const gd_patch *patches, hipStream_t s)
-{
-    PpmCache &c = ctx->ppm;
-    if ((int)c.host.size() == npatch &&
-        std::memcmp(c.host.data(), patches, npatch * sizeof(gd_patch)) == 0) {
-        if (capturing(s)) c.captured = true;
-        return GD_OK;
-    }
-    int r;
-    if ((r = prepare_rebuild(ctx, s, c.captured,
-                             { (void **)&c.d_patches, (void **)&c.d_pitems, (void **)&c.d_uitems,
-                               (void **)&c.d_soff },
-                             { &c.cap_patches, &c.cap_pitems, &c.cap_uitems, &c.cap_soff },
-                             "PPM tables")))
-        return r;
-    std::vector<gd::PatchDesc> desc(npatch);
-    std::vector<gd::PpmTile> pit;
-    std::vector<gd::PpmItem> uit;
-    std::vector<int64_t> soff(npatch);
-    int64_t off = 0;
-    for (int i = 0; i < npatch; ++i) {
-        desc[i] = to_desc(patches[i], false);
-        soff[i] = off;
-        const int64_t box = gd::ppm_box_cells(desc[i]);
-        const int64_t cells = (int64_t)patches[i].nx * patches[i].ny * patches[i].nz;
-        if (box >= 0x7fffffffLL) return fail(ctx, GD_E_ARG, "patch %d too large for the PPM step", i);
-        off += 30 * box;
-        const int e = 1, bx = patches[i].nx + 2 * e, by = patches[i].ny + 2 * e, bz = patches[i].nz + 2 * e;
-        for (int z0 = 0; z0 < bz; z0 += gd::PPM_ZRANGE)
-            for (int y0 = 0; y0 < by; y0 += gd::PPM_TILE)
-                for (int x0 = 0; x0 < bx; x0 += gd::PPM_TILE)
-                    pit.push_back(gd::PpmTile{ i, (int16_t)x0, (int16_t)y0, (int16_t)z0,
-                                               (int16_t)std::min(z0 + gd::PPM_ZRANGE, bz) });
-        for (int64_t a = 0; a < cells; a += 256) uit.push_back(gd::PpmItem{ i, (int32_t)a });
-    }
-    if (pit.size() > 0x7fffffff || uit.size() > 0x7fffffff) return fail(ctx, GD_E_ARG, "too many PPM items");
-    if ((r = ensure_capacity(ctx, &c.d_patches, &c.cap_patches, desc.size()))) return r;
-    if ((r = ensure_capacity(ctx, &c.d_pitems, &c.cap_pitems, pit.size()))) return r;
-    if ((r = ensure_capacity(ctx, &c.d_uitems, &c.cap_uitems, uit.size()))) return r;
-    if ((r = ensure_capacity(ctx, &c.d_soff, &c.cap_soff, soff.size()))) return r;
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMemcpy(c.d_patches, desc.data(), desc.size() * sizeof(gd::PatchDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c.d_pitems, pit.data(), pit.size() * sizeof(gd::PpmTile), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c.d_uitems, uit.data(), uit.size() * sizeof(gd::PpmItem), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c.d_soff, soff.data(), soff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(ctx, e, "upload of PPM tables");
-    c.host.assign(patches, patches + npatch);
-    c.npitems = (int)pit.size();
-    c.nuitems = (int)uit.size();
-    c.scratch_elems = off;
-    return GD_OK;
 }
 
 int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
@@ -623,9 +551,8 @@ int step_impl(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, int ng,
     }
     if (is_ppm(opts)) {
         if ((r = ensure_ppm_scratch(ctx, (size_t)gd::ppm_box_cells(P) * 30 * es, s))) return r;
-        int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, P, nullptr, nullptr, 0,
-                               nullptr, 0, nullptr, u_in, u_out, bflux, ctx->ppm_s.p, dt_dev, sc,
-                               ctx->d_u64, s);
+        int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, P, u_in, u_out, bflux,
+                               ctx->ppm_s.p, dt_dev, sc, ctx->d_u64, s);
         if (e) return hip_fail(ctx, e, "PPM step launch");
         if (dt_next) {
             // the CFL step of the new state, reduced over u_out
@@ -688,26 +615,19 @@ int step_batched_impl(gd_ctx *ctx, const gd_opts *opts, int npatch, const gd_pat
     hipStream_t s = (hipStream_t)hip_stream;
     const Slot slot = slot_for(ctx, s);
     if (is_ppm(opts)) {
+        // the PPM step of a batch: one persistent launch of the single-patch
+        // march over 24x8 tiles, with the fused CFL reduction
+        if ((r = build_step_tables(ctx, opts->dtype, gd::TILE_24x8, 3, npatch, patches, s,
+                                   &ctx->ppm_batch)))
+            return r;
+        const BatchCache &c = ctx->ppm_batch;
         gd::Scalars sc{ gamma, opts->rho_floor, opts->p_floor };
-        if ((r = build_ppm_tables(ctx, npatch, patches, s))) return r;
-        const PpmCache &c = ctx->ppm;
-        if ((r = ensure_ppm_scratch(ctx, (size_t)c.scratch_elems * es, s))) return r;
-        gd::PatchDesc none{};
-        int e = gd::launch_ppm(opts->dtype, opts->limiter, opts->riemann, none, c.d_patches, c.d_pitems,
-                               c.npitems, c.d_uitems, c.nuitems, c.d_soff, u_in_base, u_out_base,
-                               bflux_base, ctx->ppm_s.p, dt_dev, sc, ctx->d_u64, s);
+        gd::CflOut co{ cfl, dt_next, slot.u64 + 2, slot.u32 + 3 };
+        int e = gd::launch_ppm_batched(opts->dtype, opts->limiter, opts->riemann, c.d_patches,
+                                       c.d_items, c.nitems, u_in_base, u_out_base, bflux_base, dt_dev,
+                                       sc, ctx->d_u64, slot.u32, ctx->num_cus, co, s);
+        if (!e && dt_next) e = gd::launch_cfl_finalize(cfl, dt_next, co.smax_bits, s);
         if (e) return hip_fail(ctx, e, "PPM batched step launch");
-        if (dt_next) {
-            // the batch's CFL step, reduced over the outputs (interior layout)
-            std::vector<gd_patch> outs(patches, patches + npatch);
-            for (auto &p : outs) { p.u_in_off = p.u_out_off; p.ng = 0; }
-            if ((r = build_cfl_tables(ctx, true, npatch, outs.data(), s, &ctx->ppm_cfl))) return r;
-            const BatchCache &cc = ctx->ppm_cfl;
-            int grid = std::min(cc.ncfl, 8 * ctx->num_cus);
-            e = gd::launch_cfl(opts->dtype, cc.d_patches, cc.d_cfl_items, cc.ncfl, u_out_base, sc, cfl,
-                               dt_next, slot.u64 + 2, slot.u32 + 3, std::max(grid, 1), s);
-            if (e) return hip_fail(ctx, e, "PPM batched CFL launch");
-        }
         return GD_OK;
     }
     if ((r = build_step_tables(ctx, opts->dtype, ctx->shape_batched[opts->dtype],

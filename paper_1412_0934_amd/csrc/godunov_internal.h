@@ -184,32 +184,17 @@ int set_call_error(int code, const char *fmt, ...);
 // *dst = v, stream-ordered (capturable, unlike a host-to-device copy).
 int launch_set_scalar(double *dst, double v, hipStream_t s);
 
-// Piecewise-parabolic reconstruction (godunov_ppm.hip). A batched launch takes
-// tiles of each patch's scratch box for the predict kernel and 256-cell
-// pieces of its interior for the update kernel.
-struct PpmItem {
-    int32_t patch, start;
-};
-
-// A tile of the predict kernel: 16 x 16 columns of a patch's scratch box at
-// (x0, y0), planes [z0, z1) of the box.
-struct PpmTile {
-    int32_t patch;
-    int16_t x0, y0, z0, z1;
-};
-constexpr int PPM_TILE = 16, PPM_ZRANGE = 16;
-
+// Piecewise-parabolic reconstruction (godunov_ppm.hip).
 // Cells of a patch's PPM scratch box: the interior (periodic) or the interior
 // plus one layer (ghosted); the scratch holds 30 values per box cell.
 int64_t ppm_box_cells(const PatchDesc &P);
 
-// One PPM step (limiter 3: limited parabola, 4: unlimited). With patches ==
-// nullptr the single patch P1 is stepped; else the batch described by the
-// device tables (soff: per-patch scratch offsets in elements).
-int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-               const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
-               const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
-               const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s);
+// One PPM step of the patch P in two launches over a face-state scratch of
+// 30 values per box cell: the path of periodic boxes with an extent below 2,
+// whose wrapped stencils the single-launch march does not cover.
+int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P, const void *u_in,
+               void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
+               unsigned long long *hits, hipStream_t s);
 
 // One PPM step (limiters 3 to 6) of a single patch in one launch: the tile
 // march of the PLM step with the parabola, no face-state scratch; with
@@ -219,6 +204,15 @@ constexpr int PPM_FUSED_TX = 24, PPM_FUSED_TY = 8;
 int launch_ppm_tile(int dtype, int limiter, int riemann, const PatchDesc &P, const void *u_in,
                     void *u_out, void *bflux, const double *dt_dev, const Scalars &sc,
                     unsigned long long *hits, int min_blocks, const CflOut &co, hipStream_t s);
+// The same for a batch of ghosted patches: one persistent launch over the
+// (patch, tile, z-range) items of 24x8 tiles, the queue counters in d_queue
+// (reset by the launch's last workgroup), as many workgroups as fit on
+// num_cus compute units.
+int launch_ppm_batched(int dtype, int limiter, int riemann, const PatchDesc *d_patches,
+                       const WorkItem *d_items, int nitems, const void *u_in, void *u_out,
+                       void *bflux, const double *dt_dev, const Scalars &sc,
+                       unsigned long long *hits, unsigned *d_queue, int num_cus, const CflOut &co,
+                       hipStream_t s);
 // dt = cfl / (the maximum folded into smax_bits), which is cleared for the next use
 int launch_cfl_finalize(double cfl, double *dt_out, unsigned long long *smax_bits, hipStream_t s);
 

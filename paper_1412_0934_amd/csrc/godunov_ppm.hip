@@ -17,10 +17,12 @@
 // (Colella & Woodward 1984), plus the Hancock step's terms of the two other
 // axes.
 //
-// A single patch takes one launch per step (ppm_tile_kernel, the tile march
-// of the PLM step with the parabola: the face states stay in LDS and
-// registers). Batches, and periodic boxes thinner than two cells, take two
-// launches per step over a scratch of 30 values per predicted cell:
+// A patch takes one launch per step (ppm_tile_kernel, the tile march of the
+// PLM step with the parabola: the face states stay in LDS and registers), and
+// so does a batch (ppm_batched_kernel: the same march over a persistent work
+// queue of the batch's tiles). Periodic boxes thinner than two cells, whose
+// wrapped stencils the march does not cover, take two launches per step over
+// a scratch of 30 values per predicted cell:
 //   ppm_predict  16 x 16 column tiles of the cells whose face states some
 //                face needs (the interior and, for a ghosted patch, the face
 //                ghosts of depth 1), marching in z: each plane converted to
@@ -31,8 +33,6 @@
 //                staged states (a face shared by two cells is evaluated by
 //                both from the same inputs, so both get the same bits), the
 //                update, the boundary-flux sheets.
-// Both run over one patch (the grid covers it) or a batch (each workgroup
-// takes a tile, or a 256-cell piece, of one patch from a host-built table).
 #include "godunov_cell.h"
 #include "godunov_internal.h"
 #include "godunov_tile.h"
@@ -257,7 +257,7 @@ __device__ __forceinline__ void count_hits(int hits, unsigned long long *counter
 // through up to PZ planes; each plane of the tile and a two-deep x-y halo is
 // converted to primitives once and staged in LDS, and each column keeps the
 // primitives of planes k-2 .. k+2 in registers.
-constexpr int PT = PPM_TILE, PZ = PPM_ZRANGE, PLW = PT + 4;
+constexpr int PT = 16, PZ = 16, PLW = PT + 4;
 constexpr int PPM_HALO = PLW * PLW - PT * PT;          // 144 halo cells per plane
 
 template <typename T>
@@ -276,23 +276,14 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ u, const Addr &A,
 
 // Two waves per SIMD: the FP64 tracing variant would otherwise take 256 VGPRs
 // and 30-38 AGPRs (one wave) and runs 16% slower than with a few spills.
-template <typename T, int MODE, bool CT, bool BATCHED>
+template <typename T, int MODE, bool CT>
 __global__ __launch_bounds__(PT * PT) __attribute__((amdgpu_waves_per_eu(2))) void ppm_predict_kernel(
-    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmTile *__restrict__ tiles,
-    const int64_t *__restrict__ soff, const T *__restrict__ u_base, T *__restrict__ scratch,
-    const double *dt_dev, Scalars sc, unsigned long long *hits_ctr)
+    PatchDesc P, const T *__restrict__ u_base, T *__restrict__ scratch, const double *dt_dev,
+    Scalars sc, unsigned long long *hits_ctr)
 {
     __shared__ PpmSmem<T> sm;
-    PatchDesc P;
     int x0, y0, z0, z1;
-    int64_t so = 0;
-    if constexpr (BATCHED) {
-        const PpmTile t = tiles[blockIdx.x];
-        P = patches[t.patch];
-        x0 = t.x0; y0 = t.y0; z0 = t.z0; z1 = t.z1;
-        so = soff[t.patch];
-    } else {
-        P = P1;
+    {
         const Box Bq = make_box(P);
         const int ntx = (Bq.bx + PT - 1) / PT, nty = (Bq.by + PT - 1) / PT;
         const int b = blockIdx.x, tile = b % (ntx * nty), seg = b / (ntx * nty);
@@ -394,7 +385,7 @@ __global__ __launch_bounds__(PT * PT) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                 for (int d = 0; d < 3; ++d) S[d][q] = aR[d][q] - aL[d][q];
             }
-            T *__restrict__ out = scratch + so + ((int64_t)kb * B.by + bj) * B.bx + bi;
+            T *__restrict__ out = scratch + ((int64_t)kb * B.by + bj) * B.bx + bi;
             if constexpr (CT) {
                 const T gp = ph.gamma * W[4];
                 const T r = fast_rsqrt(gp * W[0]);
@@ -471,30 +462,18 @@ __device__ __forceinline__ void load_state(const T *__restrict__ s, int64_t n, i
     for (int q = 0; q < 5; ++q) W[q] = s[(int64_t)(slot * 5 + q) * n];
 }
 
-template <typename T, int RS, bool BATCHED>
+template <typename T, int RS>
 __global__ __launch_bounds__(PPM_BLOCK) void ppm_update_kernel(
-    PatchDesc P1, const PatchDesc *__restrict__ patches, const PpmItem *__restrict__ items,
-    const int64_t *__restrict__ soff, const T *__restrict__ u_base, const T *__restrict__ scratch,
+    PatchDesc P, const T *__restrict__ u_base, const T *__restrict__ scratch,
     T *__restrict__ out_base, T *__restrict__ bflux_base, const double *dt_dev, Scalars sc)
 {
-    PatchDesc P;
-    int start;
-    int64_t so = 0;
-    if constexpr (BATCHED) {
-        const PpmItem it = items[blockIdx.x];
-        P = patches[it.patch];
-        start = it.start;
-        so = soff[it.patch];
-    } else {
-        P = P1;
-        start = blockIdx.x * PPM_BLOCK;
-    }
+    const int start = blockIdx.x * PPM_BLOCK;
     const int64_t ncell = (int64_t)P.nx * P.ny * P.nz;
     const int idx = start + (int)threadIdx.x;
     if (idx >= ncell) return;
     const int i = idx % P.nx, j = (idx / P.nx) % P.ny, k = idx / (P.nx * P.ny);
     const Box B = make_box(P);
-    const T *__restrict__ s = scratch + so;
+    const T *__restrict__ s = scratch;
     const Phys<T> ph = make_phys<T>(sc);
     const double dt = dt_dev ? *dt_dev : P.dt;
     const T c = T(dt / P.dx);
@@ -738,28 +717,36 @@ __device__ void ppm_tile(const PatchDesc &P, const T *__restrict__ u_in_base,
             const T r = fast_rsqrt(gp * W[0]);
             const T c = gp * r, inv_c = W[0] * r;      // sqrt(gamma p / rho) and its inverse
             T lo[5], hi[5];
-            if (pre) {
-                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+            if (interior) {
+                // The prologue and epilogue planes run this same code (their
+                // x and y states are discarded, with their floor counts): the
+                // compiler may contract a * b + c differently in separate
+                // inlined copies of the tracing, and one copy for every plane
+                // keeps results independent of where z-ranges start.
+                const bool inner = !pre && !post;
+                int xyhits = 0;
+                ppm_traced_faces<0, 1, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, xyhits);
+                if (inner) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) zprev[q] = hi[q];
-            } else if (post) {
-                ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) zm[q] = lo[q];
-            } else if (interior) {
-                ppm_traced_faces<0, 1, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    sm.fl[q][Geo::xface(ci + 1, cj)] = hi[q];
-                    sm.fr[q][Geo::xface(ci, cj)] = lo[q];
+                    for (int q = 0; q < 5; ++q) {
+                        sm.fl[q][Geo::xface(ci + 1, cj)] = hi[q];
+                        sm.fr[q][Geo::xface(ci, cj)] = lo[q];
+                    }
                 }
-                ppm_traced_faces<1, 0, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, hits);
+                ppm_traced_faces<1, 0, 2>(W, winv[2], aL, aR, c, inv_c, lam, ph, lo, hi, xyhits);
+                if (inner) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] = hi[q];
-                    sm.fr[yslot(q)][Geo::yface(ci, cj)] = lo[q];
+                    for (int q = 0; q < 5; ++q) {
+                        sm.fl[yslot(q)][Geo::yface(ci, cj + 1)] = hi[q];
+                        sm.fr[yslot(q)][Geo::yface(ci, cj)] = lo[q];
+                    }
+                    hits += xyhits;
                 }
                 ppm_traced_faces<2, 0, 1>(W, winv[2], aL, aR, c, inv_c, lam, ph, zm, zpn, hits);
+                if (pre) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) zprev[q] = zpn[q];
+                }
             } else {
                 // a ring column: the traced states of its axis, the one on the
                 // tile side stored (left and bottom columns: the upper state)
@@ -980,45 +967,88 @@ int launch_ppm_tile_t(const PatchDesc &P, const void *u_in, void *u_out, void *b
     return (int)hipGetLastError();
 }
 
-template <typename T, int MODE, bool CT, int RS>
-int launch_ppm_t(const PatchDesc &P1, const PatchDesc *patches, const PpmTile *pitems, int npitems,
-                 const PpmItem *uitems, int nuitems, const int64_t *soff, const void *u_in,
-                 void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
-                 unsigned long long *hits, hipStream_t s)
+// A batch of ghosted patches, one launch: the persistent work queue of the
+// PLM batched step over (patch, tile, z-range) items, each item the march of
+// the single-patch kernel. The last workgroup to leave resets the counter.
+template <typename T, int MODE, bool CT, int RS, int TX, int TY>
+__global__ __launch_bounds__(tile_threads(TX, TY)) __attribute__((amdgpu_waves_per_eu(2)))
+void ppm_batched_kernel(const PatchDesc *__restrict__ patches, const WorkItem *__restrict__ items,
+                        int nitems, const T *__restrict__ u_in, T *__restrict__ u_out,
+                        T *__restrict__ bflux, const double *dt_dev, Scalars sc,
+                        unsigned long long *hits_ctr, unsigned *queue, CflOut co)
 {
-    if (patches) {
-        if (npitems == 0 || nuitems == 0) return 0;
-        hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, CT, true>), dim3(npitems), dim3(PT * PT), 0, s,
-                           P1, patches, pitems, soff, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
-        hipLaunchKernelGGL((ppm_update_kernel<T, RS, true>), dim3(nuitems), dim3(PPM_BLOCK), 0, s,
-                           P1, patches, uitems, soff, (const T *)u_in, (const T *)scratch, (T *)u_out,
-                           (T *)bflux, dt_dev, sc);
-        return (int)hipGetLastError();
+    __shared__ PpmTileSmem<T, TX, TY> sm;
+    __shared__ int s_item;
+    const Phys<T> ph = make_phys<T>(sc);
+    int hits = 0;
+    double smax = 0.0;
+    const bool want_cfl = co.dt_next != nullptr;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const PatchDesc P = patches[w.patch];
+        const double dt = dt_dev ? *dt_dev : P.dt;
+        const T dtdx = T(dt / P.dx), lam = T(dt / (2.0 * P.dx));
+        ppm_tile<T, MODE, CT, RS, TX, TY, true>(P, u_in, u_out, bflux, dtdx, lam, ph, w.x0, w.y0,
+                                                w.z0, w.z1, sm, hits, want_cfl, smax);
+        __syncthreads();
     }
-    const int e = P1.periodic ? 0 : 1;
-    const int64_t nbox = (int64_t)(P1.nx + 2 * e) * (P1.ny + 2 * e) * (P1.nz + 2 * e);
-    const int64_t ncell = (int64_t)P1.nx * P1.ny * P1.nz;
-    const int64_t ntiles = (int64_t)((P1.nx + 2 * e + PT - 1) / PT) * ((P1.ny + 2 * e + PT - 1) / PT) *
-                           ((P1.nz + 2 * e + PZ - 1) / PZ);
-    (void)nbox;
-    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, CT, false>), dim3((unsigned)ntiles), dim3(PT * PT), 0, s, P1,
-                       nullptr, nullptr, nullptr, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
-    hipLaunchKernelGGL((ppm_update_kernel<T, RS, false>),
-                       dim3((unsigned)((ncell + PPM_BLOCK - 1) / PPM_BLOCK)), dim3(PPM_BLOCK), 0, s, P1,
-                       nullptr, nullptr, nullptr, (const T *)u_in, (const T *)scratch, (T *)u_out,
+    flush_hits(hits, hits_ctr);
+    if (want_cfl) cfl_block_max(smax, co.smax_bits);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&queue[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
+    }
+}
+
+template <typename T, int MODE, bool CT, int RS>
+int launch_ppm_batched_t(const PatchDesc *d_patches, const WorkItem *d_items, int nitems,
+                         const void *u_in, void *u_out, void *bflux, const double *dt_dev,
+                         const Scalars &sc, unsigned long long *hits, unsigned *d_queue,
+                         int num_cus, const CflOut &co, hipStream_t s)
+{
+    constexpr int TX = PPM_FUSED_TX, TY = PPM_FUSED_TY;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ppm_batched_kernel<T, MODE, CT, RS, TX, TY>,
+                                                     TileGeom<TX, TY>::NT, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int grid = std::max(1, std::min(nitems, per_cu * num_cus));
+    hipLaunchKernelGGL((ppm_batched_kernel<T, MODE, CT, RS, TX, TY>), dim3(grid),
+                       dim3(TileGeom<TX, TY>::NT), 0, s, d_patches, d_items, nitems,
+                       (const T *)u_in, (T *)u_out, (T *)bflux, dt_dev, sc, hits, d_queue, co);
+    return (int)hipGetLastError();
+}
+
+template <typename T, int MODE, bool CT, int RS>
+int launch_ppm_t(const PatchDesc &P, const void *u_in, void *u_out, void *bflux, void *scratch,
+                 const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
+{
+    const int e = P.periodic ? 0 : 1;
+    const int64_t ncell = (int64_t)P.nx * P.ny * P.nz;
+    const int64_t ntiles = (int64_t)((P.nx + 2 * e + PT - 1) / PT) * ((P.ny + 2 * e + PT - 1) / PT) *
+                           ((P.nz + 2 * e + PZ - 1) / PZ);
+    hipLaunchKernelGGL((ppm_predict_kernel<T, MODE, CT>), dim3((unsigned)ntiles), dim3(PT * PT), 0, s,
+                       P, (const T *)u_in, (T *)scratch, dt_dev, sc, hits);
+    hipLaunchKernelGGL((ppm_update_kernel<T, RS>), dim3((unsigned)((ncell + PPM_BLOCK - 1) / PPM_BLOCK)),
+                       dim3(PPM_BLOCK), 0, s, P, (const T *)u_in, (const T *)scratch, (T *)u_out,
                        (T *)bflux, dt_dev, sc);
     return (int)hipGetLastError();
 }
 
 template <typename T>
-int launch_ppm_d(int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-                 const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
-                 const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
-                 const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
+int launch_ppm_d(int limiter, int riemann, const PatchDesc &P, const void *u_in, void *u_out,
+                 void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
+                 unsigned long long *hits, hipStream_t s)
 {
-#define GD_PPM(M, C, R) return launch_ppm_t<T, M, C, R>(P1, patches, pitems, npitems, uitems, nuitems, \
-                                                        soff, u_in, u_out, bflux, scratch, dt_dev, sc, \
-                                                        hits, s)
+#define GD_PPM(M, C, R) return launch_ppm_t<T, M, C, R>(P, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s)
     // limiters 3, 4: Hancock half step with the limited / unlimited parabola;
     // 5, 6: characteristic tracing with the limited / unlimited parabola
     const bool central = limiter == 4 || limiter == 6;
@@ -1071,22 +1101,52 @@ int launch_ppm_tile(int dtype, int limiter, int riemann, const PatchDesc &P, con
 #undef GD_PPMT
 }
 
+int launch_ppm_batched(int dtype, int limiter, int riemann, const PatchDesc *d_patches,
+                       const WorkItem *d_items, int nitems, const void *u_in, void *u_out,
+                       void *bflux, const double *dt_dev, const Scalars &sc,
+                       unsigned long long *hits, unsigned *d_queue, int num_cus, const CflOut &co,
+                       hipStream_t s)
+{
+    if (nitems <= 0) return 0;
+#define GD_PPMB(T, M, C, R) return launch_ppm_batched_t<T, M, C, R>(d_patches, d_items, nitems, u_in, \
+                                                                    u_out, bflux, dt_dev, sc, hits,   \
+                                                                    d_queue, num_cus, co, s)
+#define GD_PPMB_LIM(T, C, R)                                                    \
+    do {                                                                        \
+        if (central) GD_PPMB(T, PPM_CENTRAL, C, R);                             \
+        GD_PPMB(T, PPM_LIMITED, C, R);                                          \
+    } while (0)
+#define GD_PPMB_CT(T, R)                                                        \
+    do {                                                                        \
+        if (traced) GD_PPMB_LIM(T, true, R);                                    \
+        GD_PPMB_LIM(T, false, R);                                               \
+    } while (0)
+    const bool central = limiter == 4 || limiter == 6;
+    const bool traced = limiter == 5 || limiter == 6;
+    if (dtype == 1) {
+        if (riemann == RS_HLL) GD_PPMB_CT(float, RS_HLL);
+        GD_PPMB_CT(float, RS_HLLC);
+    }
+    if (riemann == RS_HLL) GD_PPMB_CT(double, RS_HLL);
+    GD_PPMB_CT(double, RS_HLLC);
+#undef GD_PPMB_CT
+#undef GD_PPMB_LIM
+#undef GD_PPMB
+}
+
 int64_t ppm_box_cells(const PatchDesc &P)
 {
     const int e = P.periodic ? 0 : 1;
     return (int64_t)(P.nx + 2 * e) * (P.ny + 2 * e) * (P.nz + 2 * e);
 }
 
-int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P1, const PatchDesc *patches,
-               const PpmTile *pitems, int npitems, const PpmItem *uitems, int nuitems,
-               const int64_t *soff, const void *u_in, void *u_out, void *bflux, void *scratch,
-               const double *dt_dev, const Scalars &sc, unsigned long long *hits, hipStream_t s)
+int launch_ppm(int dtype, int limiter, int riemann, const PatchDesc &P, const void *u_in,
+               void *u_out, void *bflux, void *scratch, const double *dt_dev, const Scalars &sc,
+               unsigned long long *hits, hipStream_t s)
 {
     if (dtype == 1)
-        return launch_ppm_d<float>(limiter, riemann, P1, patches, pitems, npitems, uitems, nuitems,
-                                   soff, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
-    return launch_ppm_d<double>(limiter, riemann, P1, patches, pitems, npitems, uitems, nuitems,
-                                soff, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
+        return launch_ppm_d<float>(limiter, riemann, P, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
+    return launch_ppm_d<double>(limiter, riemann, P, u_in, u_out, bflux, scratch, dt_dev, sc, hits, s);
 }
 
 }  // namespace gd

@@ -2,7 +2,9 @@
 the PPM oracle: single ghosted patches (ng = 3) and periodic boxes of ragged
 shapes, both parabolas and both Riemann solvers, FP64 to 1e-12 and FP32 to
 1e-5, outputs and boundary fluxes; free stream; device dt and the CFL step
-of the new state; a batch of uneven patches in one call; and the 256^3
+of the new state; batches of uneven patches in one call (tiny ragged ones,
+the 1024-patch batch of 8^3..32^3 every patch, and bitwise equality with the
+patches stepped one by one); and the 256^3
 periodic turbulent box at full size, checked cell by cell on a sample, each
 sampled cell from a 7^3 ghosted cut-out that the oracle steps."""
 import numpy as np
@@ -152,6 +154,63 @@ def test_batch_matches_oracle(gd, lim):
         assert bflux_err(batch.patch_flux(f, p), bref, *batch.dims[p]) <= 1e-12, p
     want = min(oracle.cfl_dt(batch.patch_out(o, p), G, 1 / 64, 0.4, periodic=True)
                for p in range(len(states)))
+    assert abs(float(host(dt_next)[0]) - want) <= 1e-14 * want
+
+
+@pytest.mark.parametrize("lim", ["ppm", "ppm_ct"])
+def test_batch_equals_its_patches_stepped_one_by_one(gd, lim):
+    """The batched launch marches the same tiles as the single-patch launch
+    (other z-ranges, another order): every patch bitwise equal, outputs and
+    boundary fluxes, FP64 and FP32."""
+    import torch
+    rng = np.random.default_rng(12)
+    dims = [tuple(int(v) for v in rng.integers(2, 31, size=3)) for _ in range(24)]
+    states = [inputs.random_patch(*d, ng=3, seed=200 + i) for i, d in enumerate(dims)]
+    batch = inputs.pack_batch(states, 3, 1 / 64, order_seed=5)
+    dt = min(oracle.cfl_dt(s, G, 1 / 64, 0.4, ng=3) for s in states)
+    table = gd.patch_table(batch.dims, 3, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, dt)
+    for dtype in (torch.float64, torch.float32):
+        say("ppm batch vs patches", lim, dtype)
+        out = torch.empty(batch.u_out_size, dtype=dtype, device="cuda")
+        fl = torch.empty(batch.flux_size, dtype=dtype, device="cuda")
+        gd.step_batched(dev(batch.u_in, dtype), table, G, out=out, bflux=fl, limiter=lim)
+        o, f = host(out), host(fl)
+        for p, st in enumerate(states):
+            a, b = gd.step(dev(st, dtype), G, 1 / 64, dt, ng=3, limiter=lim)
+            assert np.array_equal(batch.patch_out(o, p), host(a)), p
+            assert np.array_equal(batch.patch_flux(f, p), host(b).ravel()), p
+
+
+@pytest.mark.parametrize("lim", ["ppm", "ppm_ct"])
+def test_full_amr_batch_every_patch(gd, lim):
+    """1024 ghosted patches of 8^3..32^3 (ng = 3) in one persistent launch,
+    every patch against the oracle element by element, and the batch's next
+    CFL step."""
+    import torch
+    batch = inputs.amr_batch(1024, seed=5, ng=3)
+    dt = 0.4 * min(batch.dx[p] / oracle.max_signal(batch.patch_in(p), G, ng=3)
+                   for p in range(batch.npatch))
+    table = gd.patch_table(batch.dims, 3, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, dt)
+    out = torch.full((batch.u_out_size,), float("nan"), dtype=torch.float64, device="cuda")
+    fl = torch.full((batch.flux_size,), float("nan"), dtype=torch.float64, device="cuda")
+    dt_next = torch.empty(1, dtype=torch.float64, device="cuda")
+    say("ppm amr batch", lim)
+    gd.step_batched(dev(batch.u_in), table, G, out=out, bflux=fl, limiter=lim, cfl=0.4,
+                    dt_next=dt_next)
+    o, f = host(out), host(fl)
+    worst = 0.0
+    smax = 0.0
+    for p in range(batch.npatch):
+        ref, bref, _ = oracle.step(batch.patch_in(p), G, batch.dx[p], dt, ng=3, limiter=lim)
+        e = max(parity_err(batch.patch_out(o, p), ref),
+                bflux_err(batch.patch_flux(f, p), bref, *batch.dims[p]))
+        assert e <= 1e-12, (p, e)
+        worst = max(worst, e)
+        smax = max(smax, oracle.max_signal(batch.patch_out(o, p), G, periodic=True) / batch.dx[p])
+    say(f"ppm amr batch {lim}: worst patch parity {worst:.3e}")
+    want = 0.4 / smax
     assert abs(float(host(dt_next)[0]) - want) <= 1e-14 * want
 
 
