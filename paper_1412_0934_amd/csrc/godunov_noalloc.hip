@@ -337,7 +337,7 @@ extern "C" int godunov_step_batched_noalloc(const gd_opts *opts, int npatch,
     if (opts->bc != GD_GHOSTED)
         return set_call_error(GD_E_UNSUPPORTED, "the batched step takes ghosted patches only");
     if (opts->limiter < GD_MINMOD || opts->limiter > GD_UNLIMITED)
-        return set_call_error(opts->limiter <= GD_PPM_UNLIMITED ? GD_E_UNSUPPORTED : GD_E_ARG,
+        return set_call_error(opts->limiter <= GD_PPM_CT_UNLIMITED ? GD_E_UNSUPPORTED : GD_E_ARG,
                               "limiter %d is not available without allocation", opts->limiter);
     if (opts->riemann != GD_HLLC && opts->riemann != GD_HLL)
         return set_call_error(GD_E_ARG, "bad riemann solver %d", opts->riemann);

@@ -307,6 +307,7 @@ def test_noalloc_step_checks_its_arguments_on_the_host(lib):
     beyond its static scratch and NULL pointers before touching a device."""
     cases = [(_opts(), 0, 1, 1, -1), (_opts(), 65537, 1, 1, -1), (_opts(), 4, 0, 1, -1),
              (_opts(), 4, 1, 0, -1), (_opts(bc=1), 4, 1, 1, -4), (_opts(limiter=3), 4, 1, 1, -4),
+             (_opts(limiter=6), 4, 1, 1, -4), (_opts(limiter=7), 4, 1, 1, -1),
              (_opts(dtype=5), 4, 1, 1, -1)]
     for opts, npatch, pd, u, expect in cases:
         r = lib.godunov_step_batched_noalloc(ctypes.byref(opts), npatch, ctypes.c_void_p(pd),
