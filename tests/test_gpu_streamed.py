@@ -77,6 +77,27 @@ def test_streamed_equals_resident_fp64(gd, chunk, pinned):
     assert torch.equal(so, ro) and torch.equal(sf, rf)
 
 
+@pytest.mark.parametrize("shape", ["16x8+24x8", "16x8"])
+def test_streamed_in_the_tuned_tile_configurations(gd, shape):
+    """The streamed pipeline builds its chunks' work items in the batched
+    tile configuration of the context, including the per-patch 16x8 + 24x8
+    pair (the one the autotuner picks for FP32): bitwise the resident step."""
+    import torch
+    batch, _ = small_batch(n=80, seed=9)
+    table = gd.patch_table(batch.dims, 2, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, 2e-4)
+    try:
+        for dtype in (torch.float32, torch.float64):
+            gd.set_config(dtype, shape_batched=shape, zpolicy_batched=2)
+            ro, rf = resident(gd, batch, table, dtype)
+            say("streamed", shape, dtype)
+            so, sf = streamed(gd, batch, table, dtype, 2 << 20, True)
+            assert torch.equal(so, ro) and torch.equal(sf, rf)
+    finally:
+        gd.set_config(torch.float32)
+        gd.set_config(torch.float64)
+
+
 def test_streamed_fp32_and_device_dt_without_fluxes(gd):
     import torch
     batch, _ = small_batch(seed=5, order_seed=None)
