@@ -264,7 +264,7 @@ int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int
  * godunov_step_batched (same gd_patch offsets). The patches, taken in the
  * order of their input offsets, are cut into chunks whose input, output and
  * flux blocks fit chunk_bytes (>= 4096; a patch that alone exceeds it is
- * GD_E_ARG). Each chunk is copied into one of two device staging slots,
+ * GD_E_ARG). Each chunk is copied into one of three device staging slots,
  * stepped there by the batched kernel and copied back, on three streams of
  * the library's own, so that the copies of one chunk overlap the step of the
  * next; consecutive blocks contiguous in host memory move in one copy.
@@ -273,7 +273,7 @@ int gd_set_config(gd_ctx *ctx, int dtype, int shape_single, int zlen_single, int
  * hip_stream waits for its end: synchronise hip_stream before reading the
  * host outputs; the host buffers must stay valid until then. Copies overlap
  * only with pinned host memory (hipHostMalloc); pageable memory gives the
- * same results without overlap. The context keeps the staging (two slots of
+ * same results without overlap. The context keeps the staging (three slots of
  * up to chunk_bytes) and the chunk tables, rebuilt (synchronising the device)
  * when the descriptors, dtype, chunk_bytes or batched tile choice change.
  * GD_GHOSTED only; PLM limiters only (GD_E_UNSUPPORTED for PPM). */

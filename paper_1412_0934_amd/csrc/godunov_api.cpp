@@ -1347,6 +1347,11 @@ struct StreamChunk {
 
 }  // namespace
 
+// Staging slots of the streamed pipeline: chunk c uses slot c mod NSTAGE, so
+// the copy in of a chunk waits only for the step NSTAGE chunks back, and the
+// step for that chunk's copy out.
+constexpr int NSTAGE = 3;
+
 // The plan of a streamed batch: chunks of patches that fit one staging slot,
 // the device descriptors and work items of every chunk (offsets relative to
 // the slot), and the pipeline's streams, events and staging memory.
@@ -1359,10 +1364,10 @@ struct gd_stream_state {
     gd::PatchDesc *d_patches = nullptr;
     gd::WorkItem *d_items = nullptr;
     size_t cap_patches = 0, cap_items = 0;
-    void *staging = nullptr;            // two slots of in_max + out_max + fl_max elements
+    void *staging = nullptr;            // NSTAGE slots of in_max + out_max + fl_max elements
     size_t staging_bytes = 0;
     hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
-    hipEvent_t ev_in[2] = {}, ev_comp[2] = {}, ev_out[2] = {};
+    hipEvent_t ev_in[NSTAGE] = {}, ev_comp[NSTAGE] = {}, ev_out[NSTAGE] = {};
     hipEvent_t ev_start = nullptr;       // the caller's stream at the call
     bool streams = false;
 };
@@ -1374,7 +1379,7 @@ static void free_stream_state(gd_stream_state *st)
     if (st->d_items) (void)hipFree(st->d_items);
     if (st->staging) (void)hipFree(st->staging);
     if (st->streams) {
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NSTAGE; ++b) {
             (void)hipEventDestroy(st->ev_in[b]);
             (void)hipEventDestroy(st->ev_comp[b]);
             (void)hipEventDestroy(st->ev_out[b]);
@@ -1475,7 +1480,7 @@ int build_stream_plan(gd_ctx *ctx, gd_stream_state &st, const gd_opts *opts, int
     int r;
     if ((r = ensure_capacity(ctx, &st.d_patches, &st.cap_patches, desc.size()))) return r;
     if ((r = ensure_capacity(ctx, &st.d_items, &st.cap_items, items.size()))) return r;
-    const size_t need = 2 * (size_t)(in_max + out_max + fl_max) * es;
+    const size_t need = NSTAGE * (size_t)(in_max + out_max + fl_max) * es;
     hipError_t e = hipDeviceSynchronize();         // tables and staging may be in use
     if (e == hipSuccess && need > st.staging_bytes) {
         if (st.staging) (void)hipFree(st.staging);
@@ -1504,14 +1509,14 @@ int ensure_streams(gd_ctx *ctx, gd_stream_state &st)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.s_comp, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.s_out, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_start, hipEventDisableTiming);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    for (int b = 0; b < NSTAGE && e == hipSuccess; ++b) {
         e = hipEventCreateWithFlags(&st.ev_in[b], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_comp[b], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev_out[b], hipEventDisableTiming);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "streaming streams and events");
     // mark every slot free: record each event once on its (idle) stream
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    for (int b = 0; b < NSTAGE && e == hipSuccess; ++b) {
         e = hipEventRecord(st.ev_comp[b], st.s_comp);
         if (e == hipSuccess) e = hipEventRecord(st.ev_out[b], st.s_out);
     }
@@ -1579,17 +1584,17 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
     char *hout = (char *)u_out_host, *hfl = (char *)bflux_host;
     for (size_t c = 0; c < st.chunks.size() && e == hipSuccess; ++c) {
         const StreamChunk &ch = st.chunks[c];
-        const int b = (int)(c & 1);
+        const int b = (int)(c % NSTAGE);
         char *base = (char *)st.staging + (size_t)b * slot * es;
         char *sin = base, *sout = base + st.in_max * es, *sfl = sout + st.out_max * es;
-        // inputs of chunk c overwrite slot b once chunk c-2's step has read it
+        // inputs of chunk c overwrite slot b once chunk c-NSTAGE's step has read it
         e = hipStreamWaitEvent(st.s_in, st.ev_comp[b], 0);
         for (const CopyRun &run : ch.in)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(sin + run.staging * es, hin + run.host * es, run.elems * es,
                                    hipMemcpyHostToDevice, st.s_in);
         if (e == hipSuccess) e = hipEventRecord(st.ev_in[b], st.s_in);
-        // the step writes slot b's outputs once chunk c-2's have been copied out
+        // the step writes slot b's outputs once chunk c-NSTAGE's have been copied out
         if (e == hipSuccess) e = hipStreamWaitEvent(st.s_comp, st.ev_in[b], 0);
         if (e == hipSuccess) e = hipStreamWaitEvent(st.s_comp, st.ev_out[b], 0);
         if (e == hipSuccess) {
@@ -1612,7 +1617,7 @@ int godunov_step_batched_streamed(gd_ctx *ctx, const gd_opts *opts, int npatch,
                                    hipMemcpyDeviceToHost, st.s_out);
         if (e == hipSuccess) e = hipEventRecord(st.ev_out[b], st.s_out);
     }
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipStreamWaitEvent(caller, st.ev_out[b], 0);
+    for (int b = 0; b < NSTAGE && e == hipSuccess; ++b) e = hipStreamWaitEvent(caller, st.ev_out[b], 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "streamed batch");
     return GD_OK;
 }

@@ -1,5 +1,5 @@
 """Streamed batches (godunov_step_batched_streamed): a batch held in host
-memory, stepped chunk by chunk through two device staging slots with the
+memory, stepped chunk by chunk through three device staging slots with the
 copies overlapping the steps. Results must be bitwise those of the resident
 batched step on the same data -- for chunk sizes from a few patches to the
 whole batch, pinned and pageable host memory, FP64 and FP32, device dt, with
