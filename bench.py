@@ -530,7 +530,7 @@ def bench_ppm_batched(torch, gd, limiter, steps=10, warmup=2):
 bench_ppm_batched.cache = None
 
 
-def bench_streamed(torch, gd, steps=5, chunks=(64 << 20, 256 << 20)):
+def bench_streamed(torch, gd, steps=5, chunks=(64 << 20, 128 << 20, 256 << 20)):
     """The 4096-patch FP64 batch held in pinned host memory: one
     godunov_step_batched_streamed per step (chunks copied in, stepped and
     copied back on three streams, the copies overlapping the steps), against
