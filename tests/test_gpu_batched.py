@@ -225,9 +225,11 @@ def test_full_amr_batch_in_the_autotuned_configuration(gd, amr, dtype_name):
     say(f"amr batch {dtype_name} autotuned: worst patch parity {worst:.3e}")
 
 
-def test_fused_cfl_batched_step(gd):
+@pytest.mark.parametrize("shape", ["16x16", "16x8+24x8"])
+def test_fused_cfl_batched_step(gd, shape):
     """godunov_step_batched_cfl writes the same states as the plain batched
-    step and dt_next = min over patches of C dx_p / s_p of the new states."""
+    step and dt_next = min over patches of C dx_p / s_p of the new states,
+    with one tile shape and with the per-patch pair."""
     import torch
     batch = small_batch(seed=25)
     table = gd.patch_table(batch.dims, batch.ng, batch.u_in_off, batch.u_out_off, batch.flux_off,
@@ -236,12 +238,16 @@ def test_fused_cfl_batched_step(gd):
     dt = gd.cfl_dt_batched(u_in, table, G, 0.5)
     out1 = torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda")
     out2 = torch.empty_like(out1)
-    say("fused batched: plain")
-    gd.step_batched(u_in, table, G, out=out1, dt_dev=dt)
     nxt = torch.empty(1, dtype=torch.float64, device="cuda")
-    say("fused batched: with cfl")
-    gd.step_batched(u_in, table, G, out=out2, dt_dev=dt, cfl=0.5, dt_next=nxt)
-    o1, o2 = host(out1), host(out2)
+    try:
+        gd.set_config(torch.float64, shape_batched=shape, zpolicy_batched=2)
+        say("fused batched: plain", shape)
+        gd.step_batched(u_in, table, G, out=out1, dt_dev=dt)
+        say("fused batched: with cfl", shape)
+        gd.step_batched(u_in, table, G, out=out2, dt_dev=dt, cfl=0.5, dt_next=nxt)
+        o1, o2 = host(out1), host(out2)
+    finally:
+        gd.set_config(torch.float64)
     assert np.array_equal(o1, o2)
     ref = min(0.5 * batch.dx[p] / oracle.max_signal(batch.patch_out(o1, p), G, periodic=True)
               for p in range(batch.npatch))
