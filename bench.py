@@ -384,6 +384,13 @@ def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
     gd.cfl_dt(ci, GAMMA, h.dx_coarse / 2, 0.5, periodic=True, out=dt)
     fine_table = gd.patch_table(h.n, 2, f.u_in_off, f.u_out_off, f.flux_off, h.dx_coarse / 2, 0.0)
     stream = torch.cuda.current_stream()
+    # the fine level's patches (4..24 cells per axis) are smaller than the
+    # 4096-patch batch's: tune the batched step on them, as a user of the
+    # hierarchy would, and restore the batch's configuration afterwards
+    keep = gd.get_config(torch.float64)
+    gd.autotune_batched(fi, fine_table, GAMMA, out=fo, bflux=ff)
+    fine_config = gd.get_config(torch.float64)
+    log(f"bench: AMR fine level config {fine_config}")
 
     def step():
         plan.step(ci, fi, GAMMA, dt_dev=dt, coarse_out=co, fine_out=fo, fine_flux=ff)
@@ -421,10 +428,13 @@ def bench_amr(torch, gd, steps=10, warmup=2, nc=128, nfine=1024, max_size=12):
     ghosts = int((np.prod(d + 4, axis=1) - np.prod(d, axis=1)).sum())
     cells = nc ** 3 + fine_cells
     fill_bytes = 2 * 5 * 8 * ghosts
+    gd.set_config(torch.float64, **keep)
     return {"workload": f"two-level AMR: periodic {nc}^3 coarse box + {len(h.lo)} disjoint fine "
                         f"patches refined by 2 (2..{max_size} coarse cells per axis, {fine_cells} "
                         "fine cells), smooth random Fourier state, minmod + HLLC, FP64, one "
                         "gd_amr_step per step (5 launches, dt on the device)",
+            "fine_config": {"shape_batched": fine_config["shape_batched"],
+                            "zpolicy_batched": fine_config["zpolicy_batched"]},
             "patches": int(len(h.lo)), "coarse_cells": nc ** 3, "fine_cells": fine_cells,
             "ghost_cells": ghosts, "ms_per_step": round(ms, 4),
             "mcell_per_s": cells / (ms * 1e-3) / 1e6, "stage_ms": stage_ms,
