@@ -805,9 +805,9 @@ int gd_autotune_step(gd_ctx *ctx, const gd_opts *opts, int nx, int ny, int nz, i
                             gd::TILE_24x8 };
     const int zlens[3] = { 16, 32, 64 };
     const int keep_shape = ctx->shape_single[dt_i], keep_zlen = ctx->zlen_single[dt_i];
-    // round 0 runs every candidate once (clocks and caches settle); rounds 1
-    // and 2 time each candidate over 4 calls; a candidate's time is its best
-    // round, so a transient slowdown does not decide the choice
+    // the first pass runs every candidate once (clocks and caches settle);
+    // the next two time each candidate over 4 calls; a candidate's time is its
+    // best pass, so a transient slowdown does not decide the choice
     float best_ms[15];
     for (float &m : best_ms) m = 1e30f;
     for (int round = 0; round < 3; ++round)
