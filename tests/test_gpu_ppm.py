@@ -3,8 +3,8 @@ the PPM oracle: single ghosted patches (ng = 3) and periodic boxes of ragged
 shapes, both parabolas and both Riemann solvers, FP64 to 1e-12 and FP32 to
 1e-5, outputs and boundary fluxes; free stream; device dt and the CFL step
 of the new state; batches of uneven patches in one call (tiny ragged ones,
-the 1024-patch batch of 8^3..32^3 every patch, and bitwise equality with the
-patches stepped one by one); and the 256^3
+the 1024-patch batch of 8^3..32^3 every patch, bitwise equality with the
+patches stepped one by one, and replays of a captured HIP graph); and the 256^3
 periodic turbulent box at full size, checked cell by cell on a sample, each
 sampled cell from a 7^3 ghosted cut-out that the oracle steps."""
 import numpy as np
@@ -180,6 +180,65 @@ def test_batch_equals_its_patches_stepped_one_by_one(gd, lim):
             a, b = gd.step(dev(st, dtype), G, 1 / 64, dt, ng=3, limiter=lim)
             assert np.array_equal(batch.patch_out(o, p), host(a)), p
             assert np.array_equal(batch.patch_flux(f, p), host(b).ravel()), p
+
+
+@pytest.mark.parametrize("lim", ["ppm", "ppm_ct"])
+def test_batch_in_a_hip_graph(gd, lim):
+    """Two chained batched steps with the fused CFL reduction (the second
+    takes the first's next step from the device) captured in one HIP graph and
+    replayed with eager work and synchronisations between the replays: every
+    replay bitwise equal to the eager calls, whose first step matches the
+    oracle. The persistent launch leaves its work counter at zero and the CFL
+    finish leaves its accumulator cleared, so no replay needs a reset."""
+    import torch
+    rng = np.random.default_rng(21)
+    dims = [tuple(int(v) for v in rng.integers(2, 27, size=3)) for _ in range(48)]
+    states = [inputs.random_patch(*d, ng=3, seed=300 + i) for i, d in enumerate(dims)]
+    batch = inputs.pack_batch(states, 3, 1 / 64, order_seed=6)
+    dt = min(oracle.cfl_dt(s, G, 1 / 64, 0.4, ng=3) for s in states)
+    table = gd.patch_table(batch.dims, 3, batch.u_in_off, batch.u_out_off, batch.flux_off,
+                           batch.dx, dt)
+    u_in = dev(batch.u_in)
+    outs = [torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda") for _ in range(2)]
+    fls = [torch.empty(batch.flux_size, dtype=torch.float64, device="cuda") for _ in range(2)]
+    dts = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+
+    def steps():
+        gd.step_batched(u_in, table, G, out=outs[0], bflux=fls[0], limiter=lim, cfl=0.4,
+                        dt_next=dts[0])
+        gd.step_batched(u_in, table, G, out=outs[1], bflux=fls[1], dt_dev=dts[0], limiter=lim,
+                        cfl=0.4, dt_next=dts[1])
+
+    say("ppm graph: eager reference", lim)
+    steps()
+    ref = [host(t) for t in outs + fls + dts]
+    for p in range(0, len(states), 12):
+        want, _, _ = oracle.step(states[p], G, 1 / 64, dt, ng=3, limiter=lim)
+        assert parity_err(batch.patch_out(ref[0], p), want) <= 1e-12, p
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        steps()                     # warm-up on another stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("ppm graph: capture", lim)
+    with torch.cuda.graph(g):
+        steps()
+    for r in range(4):
+        for t in outs + fls:
+            t.fill_(float("nan"))
+        for t in dts:
+            t.fill_(0.0)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()   # eager work
+        torch.cuda.synchronize()
+        say("ppm graph: replay", r)
+        g.replay()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        got = [host(t) for t in outs + fls + dts]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), r
 
 
 @pytest.mark.parametrize("lim", ["ppm", "ppm_ct"])
