@@ -123,27 +123,41 @@ def test_autotuner_picks_a_configuration_that_keeps_parity(gd):
         gd.set_config(torch.float64)
 
 
-def test_batched_step_in_a_hip_graph(gd):
+@pytest.mark.parametrize("dtype_name,shape,pol", [("f64", "16x16", 1), ("f64", "16x8", 2),
+                                                   ("f32", "16x8+24x8", 2)])
+def test_batched_step_in_a_hip_graph(gd, dtype_name, shape, pol):
     """Capture cfl_dt + godunov_step_batched in a graph; replay it several
     times with eager work and synchronisations between replays, each replay
-    checked against the eager result."""
+    checked against the eager result. The default configuration and the two
+    the autotuner picks for the AMR batch (16x8 tiles in FP64, the tile pair
+    in FP32, whole-patch z-ranges)."""
     import torch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
     rng = np.random.default_rng(43)
     states = [inputs.random_patch(*(int(v) for v in rng.integers(4, 26, size=3)), seed=200 + p)
               for p in range(40)]
     batch = inputs.pack_batch(states, 2, 1 / 128, order_seed=4)
     table = gd.patch_table(batch.dims, 2, batch.u_in_off, batch.u_out_off, batch.flux_off,
                            batch.dx, 0.0)
-    u_in = torch.from_numpy(batch.u_in).cuda()
-    out = torch.empty(batch.u_out_size, dtype=torch.float64, device="cuda")
-    flux = torch.empty(batch.flux_size, dtype=torch.float64, device="cuda")
+    u_in = torch.from_numpy(batch.u_in).cuda().to(dtype)
+    out = torch.empty(batch.u_out_size, dtype=dtype, device="cuda")
+    flux = torch.empty(batch.flux_size, dtype=dtype, device="cuda")
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    gd.set_config(dtype, shape_batched=shape, zpolicy_batched=pol)
+    try:
+        _replay_batched_graph(gd, batch, table, u_in, out, flux, dt, (dtype_name, shape, pol))
+    finally:
+        gd.set_config(dtype)
+
+
+def _replay_batched_graph(gd, batch, table, u_in, out, flux, dt, what):
+    import torch
 
     def step():
         gd.cfl_dt_batched(u_in, table, G, 0.5, out=dt)
         gd.step_batched(u_in, table, G, out=out, bflux=flux, dt_dev=dt)
 
-    say("graph: eager reference")
+    say("graph: eager reference", *what)
     step()
     ref_out, ref_flux, ref_dt = host(out), host(flux), host(dt)
     side = torch.cuda.Stream()
@@ -153,7 +167,7 @@ def test_batched_step_in_a_hip_graph(gd):
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    say("graph: capture")
+    say("graph: capture", *what)
     with torch.cuda.graph(g):
         step()
     for r in range(4):
@@ -162,7 +176,7 @@ def test_batched_step_in_a_hip_graph(gd):
         dt.fill_(0.0)
         junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()   # eager work
         torch.cuda.synchronize()
-        say("graph: replay", r)
+        say("graph: replay", *what, r)
         g.replay()
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
