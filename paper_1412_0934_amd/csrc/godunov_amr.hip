@@ -174,7 +174,9 @@ __global__ __launch_bounds__(SEAM_BLOCK) void face_state_kernel(AmrTables t,
 {
     const int g = blockIdx.x * SEAM_BLOCK + threadIdx.x;
     if (g >= 2 * t.nfaces) return;
-    const int side = g >= t.nfaces, f = g - side * t.nfaces;
+    // the two sides of a face in neighbouring lanes: their stencils share the
+    // cells next to the face, so a wave fetches those lines once
+    const int side = g & 1, f = g >> 1;
     const double dt = dt_dev ? *dt_dev : dt_host;
     const T lam = T(dt / (2.0 * dx));
     const Phys<T> ph = make_phys<T>(sc);
